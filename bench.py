@@ -1,0 +1,160 @@
+#!/usr/bin/env python3
+"""Benchmark of the IRE tracing hot path on one MI355X.
+
+One step = one complete IRE run of the benchmark cloud: zero the absorbed-
+energy accumulators, trace every package (launch, shell stepping, scattering,
+absorption with immediate re-emission, escape), and finalize the per-shell
+temperatures into device memory.  The model's tables and shells are resident
+on the device before the timed region (they are built once per model).
+
+Prints ONE JSON line (see the fields below).  `roofline` reports the tracing
+kernel against the VALU issue peak: algorithmic work = sum over event types of
+(events of that type in the launch) x (VALU instructions that event's path
+executes per lane), divided by the kernel duration measured with HIP events on
+the launch stream.  `cpu_baseline` times the FP64 oracle on the host cores on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# VALU instructions one lane executes per event on the FP32 tracer's paths
+# (least-squares fit of SQ_INSTS_VALU over one-lane runs of several clouds;
+# the fit and the command that produced it are kept under profiles/).
+VALU_PER_EVENT = {"cross": 34.0, "launch": 330.0, "scat": 250.0, "abs": 520.0}
+
+# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = VALU lane-instruction issue peak
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+WORKLOADS = {
+    # name: (factory, packages, description)
+    "ext101_tauV10_1e8": ("cfg_external_large", 100_000_000,
+                          "external sphere, 101 equal shells, central tau_V=10, 1e8 packages"),
+    "central200_tauV100_1e8": ("cfg_central", 100_000_000,
+                               "central 5000 K 1 Lsun source, 200 log shells 10 AU-0.1 pc, tau_V=100, 1e8 packages"),
+    "ext50_tauV1_1e5": ("cfg_external_small", 100_000,
+                        "external sphere, 50 equal shells, central tau_V=1, 1e5 packages"),
+}
+
+
+def algorithmic_ops(stats: dict) -> float:
+    return (VALU_PER_EVENT["cross"] * stats["n_cross"] + VALU_PER_EVENT["launch"] * stats["n_launch"]
+            + VALU_PER_EVENT["scat"] * stats["n_scat"] + VALU_PER_EVENT["abs"] * stats["n_abs"])
+
+
+def cpu_baseline(model: dict, key: str, n_pkg_per_seed: int, seeds: int, stepping_note: str) -> dict:
+    import oracle
+    oracle.build(force=False)
+    threads = max(1, min(16, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    kw = {key: n_pkg_per_seed}
+    oracle.ensemble(model, seeds=range(1, seeds + 1), threads=threads, **kw)
+    dt = time.perf_counter() - t0
+    return {"value": seeds * n_pkg_per_seed / dt, "unit": "packages/s", "cores": threads, "kind": "oracle",
+            "sample": f"{seeds} independent seeds x {n_pkg_per_seed:.0e} packages of the same cloud, "
+                      f"serial FP64 oracle, {threads} threads, {dt:.1f} s wall ({stepping_note})"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="ext101_tauV10_1e8", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+              file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_2408_13807_amd import ire, workloads
+
+    factory, n_pkg, desc = WORKLOADS[args.workload]
+    model = getattr(workloads, factory)()
+    key = "n_ps" if model.get("J") is None else "n_ext"
+    n = len(model["rho"])
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    A = torch.zeros(n, dtype=torch.float64, device="cuda")
+    T = torch.zeros(n, dtype=torch.float64, device="cuda")
+
+    h = ire.IREModel(0)
+    h.set_model(model)
+    h.set_options()
+
+    def step(seed: int):
+        h.run(seed=seed, stream=stream, **{key: n_pkg})
+        h.results_dev(A.data_ptr(), T.data_ptr(), stream=stream)
+
+    for w in range(args.warmup):
+        step(10_000 + w)
+    torch.cuda.synchronize()
+
+    kernel_ms = []
+    events = None
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(1 + s)
+        st = h.stats()           # synchronises; tracing-kernel time from HIP events on `stream`
+        kernel_ms.append(st["ms_trace"])
+        events = st if events is None else {k: events[k] + st[k] for k in ("n_cross", "n_launch", "n_scat", "n_abs")}
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+
+    # PCIe-inclusive rate: host model in, host results out (reported, not the value)
+    tp0 = time.perf_counter()
+    h.set_model(model)
+    h.run(seed=99, **{key: n_pkg})
+    host_res = h.results()
+    tp1 = time.perf_counter()
+
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = n_pkg * args.steps / (t1 - t0)
+    k_ms = sum(kernel_ms) / len(kernel_ms)
+    per_launch = {k: events[k] / args.steps for k in ("n_cross", "n_launch", "n_scat", "n_abs")}
+    ops = algorithmic_ops(per_launch)
+    achieved = ops / (k_ms * 1e-3) / 1e12
+    line = {
+        "metric": "photon packages/s (IRE tracing, one cloud model)",
+        "value": value,
+        "unit": "packages/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": desc, "shells": n, "packages": n_pkg,
+                   "stepping": "fp32", "accumulators": "fp64", "parallelism": "single GPU"},
+        "kernel_ms_avg": k_ms,
+        "kernel_packages_per_s": n_pkg / (k_ms * 1e-3),
+        "events_per_launch": per_launch,
+        "pcie_inclusive_packages_per_s": n_pkg / (tp1 - tp0),
+        "T_center_K": float(host_res["T"][0]),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
+                     "unit": "TOP/s (VALU lane-instructions)", "frac": achieved / VALU_PEAK_TOPS,
+                     "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(model, key, 500_000, 16, "same cloud, same package budget per seed")
+    h.close()
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,642 @@
+// C-ABI of libire (include/ire.h): argument validation, host-side FP64 table
+// construction, device buffers and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ire.h"
+#include "ire_internal.h"
+
+namespace ire {
+int trace_block_fp32();
+}
+
+namespace {
+
+constexpr double kH = 6.62607015e-27;   // erg s
+constexpr double kKB = 1.380649e-16;    // erg / K
+constexpr double kC = 2.99792458e10;    // cm / s
+constexpr double kPi = 3.14159265358979323846;
+
+// Planck intensity B_nu(T); 0 for T <= 0 and where exp(h nu / kT) overflows.
+double planck(double nu, double T) {
+    if (!(T > 0.0)) return 0.0;
+    const double x = kH * nu / (kKB * T);
+    if (x > 700.0) return 0.0;
+    return (2.0 * kH / (kC * kC)) * nu * nu * nu / std::expm1(x);
+}
+
+// Normalised cumulative sums of q into out (the last entry exactly 1).
+void cumulative(const double *q, int K, double *out) {
+    double total = 0.0;
+    for (int k = 0; k < K; ++k) total += q[k];
+    double run = 0.0;
+    for (int k = 0; k < K; ++k) {
+        run += q[k];
+        out[k] = total > 0.0 ? run / total : 1.0;
+    }
+    out[K - 1] = 1.0;
+}
+
+template <typename T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    hipError_t ensure(size_t count) {
+        if (count <= n && p) return hipSuccess;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+        hipError_t e = hipMalloc(reinterpret_cast<void **>(&p), std::max<size_t>(count, 1) * sizeof(T));
+        if (e == hipSuccess) n = count;
+        return e;
+    }
+    hipError_t upload(const std::vector<T> &h) {
+        hipError_t e = ensure(h.size());
+        if (e != hipSuccess) return e;
+        return hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+}  // namespace
+
+struct ire_model {
+    int device = 0;
+    std::string err;
+    // problem definition (host, FP64)
+    std::vector<double> r_edges, rho;
+    std::vector<double> nu, kabs, albedo, g;
+    double t_min = 3.0, t_max = 1600.0;
+    int n_t = 512;
+    std::vector<double> J;          // empty = no external field
+    double L_ps = 0.0;
+    std::vector<double> S;          // empty = no point source
+    ire_options opt{};
+    bool dirty = true;
+    // derived host tables
+    double L_ext = 0.0;
+    std::vector<double> lnT, lnG;
+    // device buffers
+    DevBuf<ire::ShellF> shf;
+    DevBuf<ire::ShellD> shd;
+    DevBuf<ire::DustF> dustf;
+    DevBuf<ire::DustD> dustd;
+    DevBuf<float> cdff, Gf, Df;
+    DevBuf<double> cdfd, Gd, Dd, invM, lnGd, lnTd;
+    DevBuf<double> A, A_out, T_out;
+    DevBuf<ire::DevStats> stats;
+    // run state
+    bool begun = false;
+    unsigned long long n_total[2] = {0, 0};
+    unsigned long long n_done[2] = {0, 0};
+    unsigned long long seed = 0;
+    double eps[2] = {0.0, 0.0};
+    hipStream_t last_stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    float ms_tables = 0.0f, ms_trace = 0.0f, ms_finalize = 0.0f;
+    bool timed = false;
+    int n_cu = 0;
+    size_t max_lds = 0;
+
+    int fail(int code, const char *fmt, ...) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        err = buf;
+        return code;
+    }
+    int hip_fail(hipError_t e, const char *what) {
+        return fail(IRE_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+    }
+};
+
+namespace {
+
+bool finite_all(const double *a, size_t n) {
+    for (size_t j = 0; j < n; ++j)
+        if (!std::isfinite(a[j])) return false;
+    return true;
+}
+
+// Build every table in FP64 on the host and upload FP32 and FP64 copies.
+int build_tables(ire_model *m) {
+    const int n = (int)m->rho.size();
+    const int K = (int)m->nu.size();
+    const int nt = m->n_t;
+    const double Rout = m->r_edges[n];
+
+    // trapezoid weights in linear frequency
+    std::vector<double> w(K);
+    if (K == 1) {
+        w[0] = 1.0;
+    } else {
+        for (int k = 0; k < K; ++k) {
+            const double left = k > 0 ? m->nu[k] - m->nu[k - 1] : 0.0;
+            const double right = k + 1 < K ? m->nu[k + 1] - m->nu[k] : 0.0;
+            w[k] = 0.5 * (left + right);
+        }
+    }
+
+    // shells
+    std::vector<ire::ShellF> shf(n);
+    std::vector<ire::ShellD> shd(n);
+    std::vector<double> invM(n);
+    for (int i = 0; i < n; ++i) {
+        const double a = m->r_edges[i] / Rout, b = m->r_edges[i + 1] / Rout;
+        shd[i] = ire::ShellD{a * a, b * b, m->rho[i] * Rout, a};
+        shf[i] = ire::ShellF{(float)(a * a), (float)(b * b), (float)(m->rho[i] * Rout), (float)a};
+        const double r0 = m->r_edges[i], r1 = m->r_edges[i + 1];
+        const double M = m->rho[i] * (4.0 * kPi / 3.0) * (r1 * r1 * r1 - r0 * r0 * r0);
+        invM[i] = M > 0.0 ? 1.0 / M : 0.0;
+    }
+    // the outermost edge is exactly 1 in both precisions
+    shd[n - 1].r2_out = 1.0;
+    shf[n - 1].r2_out = 1.0f;
+
+    // dust
+    std::vector<ire::DustF> df(K);
+    std::vector<ire::DustD> dd(K);
+    for (int k = 0; k < K; ++k) {
+        const double kS = m->kabs[k] * m->albedo[k] / (1.0 - m->albedo[k]);
+        dd[k] = ire::DustD{m->kabs[k], kS, m->g[k], m->albedo[k]};
+        df[k] = ire::DustF{(float)m->kabs[k], (float)kS, (float)m->g[k], (float)m->albedo[k]};
+    }
+
+    // sources: frequency CDFs of J w and S w
+    std::vector<double> q(K), cdf(2 * K);
+    double sumJ = 0.0;
+    for (int k = 0; k < K; ++k) {
+        q[k] = m->J.empty() ? 0.0 : m->J[k] * w[k];
+        sumJ += q[k];
+    }
+    cumulative(q.data(), K, cdf.data());
+    for (int k = 0; k < K; ++k) q[k] = m->S.empty() ? 0.0 : m->S[k] * w[k];
+    cumulative(q.data(), K, cdf.data() + K);
+    m->L_ext = 4.0 * kPi * Rout * Rout * kPi * sumJ;
+
+    // temperature grid, G(T) = 4 pi sum kappa_abs B w, and the re-emission rows:
+    // row 0 holds kappa_abs B(T_0) w (absorbed power below the first point),
+    // row j >= 1 holds kappa_abs [B(T_j) - B(T_{j-1})] w
+    std::vector<double> Tg(nt), G(nt), D((size_t)nt * K);
+    m->lnT.assign(nt, 0.0);
+    m->lnG.assign(nt, 0.0);
+    std::vector<double> Bprev(K, 0.0), Bcur(K);
+    for (int j = 0; j < nt; ++j) {
+        Tg[j] = m->t_min * std::pow(m->t_max / m->t_min, (double)j / (double)(nt - 1));
+        double acc = 0.0;
+        for (int k = 0; k < K; ++k) {
+            Bcur[k] = planck(m->nu[k], Tg[j]);
+            acc += m->kabs[k] * Bcur[k] * w[k];
+            q[k] = m->kabs[k] * (Bcur[k] - (j == 0 ? 0.0 : Bprev[k])) * w[k];
+        }
+        G[j] = 4.0 * kPi * acc;
+        m->lnT[j] = std::log(Tg[j]);
+        m->lnG[j] = std::log(G[j]);
+        cumulative(q.data(), K, D.data() + (size_t)j * K);
+        Bprev.swap(Bcur);
+    }
+    for (int j = 1; j < nt; ++j)
+        if (!(G[j] > G[j - 1]))
+            return m->fail(IRE_E_INVALID, "G(T) is not increasing on the temperature grid at point %d", j);
+    if (!(G[0] > 0.0)) return m->fail(IRE_E_INVALID, "G(t_min) underflows: raise t_min");
+
+    std::vector<float> cdff(cdf.begin(), cdf.end()), Gf(G.begin(), G.end()), Df(D.begin(), D.end());
+    hipError_t e;
+    if ((e = hipSetDevice(m->device)) != hipSuccess) return m->hip_fail(e, "hipSetDevice");
+    if ((e = m->shf.upload(shf)) != hipSuccess || (e = m->shd.upload(shd)) != hipSuccess ||
+        (e = m->dustf.upload(df)) != hipSuccess || (e = m->dustd.upload(dd)) != hipSuccess ||
+        (e = m->cdff.upload(cdff)) != hipSuccess || (e = m->cdfd.upload(cdf)) != hipSuccess ||
+        (e = m->Gf.upload(Gf)) != hipSuccess || (e = m->Gd.upload(G)) != hipSuccess ||
+        (e = m->Df.upload(Df)) != hipSuccess || (e = m->Dd.upload(D)) != hipSuccess ||
+        (e = m->invM.upload(invM)) != hipSuccess || (e = m->lnGd.upload(m->lnG)) != hipSuccess ||
+        (e = m->lnTd.upload(m->lnT)) != hipSuccess)
+        return e == hipErrorOutOfMemory ? m->fail(IRE_E_NOMEM, "device allocation failed")
+                                        : m->hip_fail(e, "table upload");
+    if ((e = m->A.ensure((size_t)n * ire::kAccStride)) != hipSuccess ||
+        (e = m->A_out.ensure(n)) != hipSuccess || (e = m->T_out.ensure(n)) != hipSuccess ||
+        (e = m->stats.ensure(1)) != hipSuccess)
+        return m->fail(IRE_E_NOMEM, "device allocation failed: %s", hipGetErrorString(e));
+    m->dirty = false;
+    return IRE_OK;
+}
+
+int check_ready(ire_model *m) {
+    if (m->rho.empty()) return m->fail(IRE_E_STATE, "shells are not set");
+    if (m->nu.empty()) return m->fail(IRE_E_STATE, "dust is not set");
+    if (!m->J.empty() && m->J.size() != m->nu.size())
+        return m->fail(IRE_E_STATE, "external field was set for a different frequency grid");
+    if (!m->S.empty() && m->S.size() != m->nu.size())
+        return m->fail(IRE_E_STATE, "point-source spectrum was set for a different frequency grid");
+    return IRE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ire_default_options(ire_options *o) {
+    if (!o) return IRE_E_INVALID;
+    o->k_bg = 0.5;
+    o->ffi = 0;
+    o->w_floor = 1e-10;
+    o->max_events = 1000000;
+    o->stepping = IRE_FP32;
+    o->max_lanes = 0;
+    o->reemit_uniform = 0;
+    o->aggregate = 1;
+    o->batch = 0;
+    return IRE_OK;
+}
+
+int ire_create(int hip_device, ire_model **out) {
+    if (!out) return IRE_E_INVALID;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || hip_device < 0 || hip_device >= count)
+        return IRE_E_DEVICE;
+    ire_model *m = new (std::nothrow) ire_model();
+    if (!m) return IRE_E_NOMEM;
+    m->device = hip_device;
+    ire_default_options(&m->opt);
+    if (hipSetDevice(hip_device) != hipSuccess ||
+        hipDeviceGetAttribute(&m->n_cu, hipDeviceAttributeMultiprocessorCount, hip_device) != hipSuccess) {
+        delete m;
+        return IRE_E_DEVICE;
+    }
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, hip_device) != hipSuccess) {
+        delete m;
+        return IRE_E_DEVICE;
+    }
+    m->max_lds = (size_t)lds;
+    if (hipEventCreate(&m->ev0) != hipSuccess || hipEventCreate(&m->ev1) != hipSuccess) {
+        delete m;
+        return IRE_E_DEVICE;
+    }
+    *out = m;
+    return IRE_OK;
+}
+
+void ire_destroy(ire_model *m) {
+    if (!m) return;
+    (void)hipSetDevice(m->device);
+    (void)hipDeviceSynchronize();
+    m->shf.release(); m->shd.release(); m->dustf.release(); m->dustd.release();
+    m->cdff.release(); m->Gf.release(); m->Df.release(); m->cdfd.release(); m->Gd.release();
+    m->Dd.release(); m->invM.release(); m->lnGd.release(); m->lnTd.release(); m->A.release();
+    m->A_out.release(); m->T_out.release(); m->stats.release();
+    if (m->ev0) (void)hipEventDestroy(m->ev0);
+    if (m->ev1) (void)hipEventDestroy(m->ev1);
+    delete m;
+}
+
+const char *ire_last_error(const ire_model *m) {
+    return m ? m->err.c_str() : "null handle";
+}
+
+int ire_set_shells(ire_model *m, int32_t n, const double *r_edges, const double *rho) {
+    if (!m) return IRE_E_INVALID;
+    if (n < 1 || !r_edges || !rho) return m->fail(IRE_E_INVALID, "need n >= 1 shells and both arrays");
+    if (!finite_all(r_edges, n + 1) || !finite_all(rho, n)) return m->fail(IRE_E_INVALID, "non-finite shell data");
+    if (!(r_edges[0] >= 0.0)) return m->fail(IRE_E_INVALID, "r_edges[0] must be >= 0");
+    for (int i = 0; i < n; ++i) {
+        if (!(r_edges[i + 1] > r_edges[i])) return m->fail(IRE_E_INVALID, "r_edges must increase strictly (index %d)", i);
+        if (!(rho[i] >= 0.0)) return m->fail(IRE_E_INVALID, "rho[%d] < 0", i);
+    }
+    m->r_edges.assign(r_edges, r_edges + n + 1);
+    m->rho.assign(rho, rho + n);
+    m->dirty = true;
+    m->begun = false;
+    return IRE_OK;
+}
+
+int ire_set_dust(ire_model *m, int32_t K, const double *nu, const double *kappa_abs,
+                 const double *albedo, const double *g) {
+    if (!m) return IRE_E_INVALID;
+    if (K < 1 || !nu || !kappa_abs || !albedo || !g) return m->fail(IRE_E_INVALID, "need K >= 1 and all dust arrays");
+    if (!finite_all(nu, K) || !finite_all(kappa_abs, K) || !finite_all(albedo, K) || !finite_all(g, K))
+        return m->fail(IRE_E_INVALID, "non-finite dust data");
+    for (int k = 0; k < K; ++k) {
+        if (!(nu[k] > 0.0) || (k > 0 && !(nu[k] > nu[k - 1]))) return m->fail(IRE_E_INVALID, "nu must be positive and increase strictly (index %d)", k);
+        if (!(kappa_abs[k] > 0.0)) return m->fail(IRE_E_INVALID, "kappa_abs[%d] must be > 0", k);
+        if (!(albedo[k] >= 0.0 && albedo[k] < 1.0)) return m->fail(IRE_E_INVALID, "albedo[%d] must be in [0,1)", k);
+        if (!(g[k] > -1.0 && g[k] < 1.0)) return m->fail(IRE_E_INVALID, "g[%d] must be in (-1,1)", k);
+    }
+    if (!m->J.empty() && (int)m->J.size() != K) m->J.clear();
+    if (!m->S.empty() && (int)m->S.size() != K) { m->S.clear(); m->L_ps = 0.0; }
+    m->nu.assign(nu, nu + K);
+    m->kabs.assign(kappa_abs, kappa_abs + K);
+    m->albedo.assign(albedo, albedo + K);
+    m->g.assign(g, g + K);
+    m->dirty = true;
+    m->begun = false;
+    return IRE_OK;
+}
+
+int ire_set_temperature_grid(ire_model *m, double t_min, double t_max, int32_t n_t) {
+    if (!m) return IRE_E_INVALID;
+    if (!(t_min > 0.0) || !(t_max > t_min) || !std::isfinite(t_max) || n_t < 2)
+        return m->fail(IRE_E_INVALID, "need 0 < t_min < t_max and n_t >= 2");
+    m->t_min = t_min;
+    m->t_max = t_max;
+    m->n_t = n_t;
+    m->dirty = true;
+    m->begun = false;
+    return IRE_OK;
+}
+
+int ire_set_external_field(ire_model *m, const double *J_nu) {
+    if (!m) return IRE_E_INVALID;
+    if (!J_nu) { m->J.clear(); m->dirty = true; m->begun = false; return IRE_OK; }
+    if (m->nu.empty()) return m->fail(IRE_E_STATE, "set the dust (frequency grid) before the external field");
+    const int K = (int)m->nu.size();
+    if (!finite_all(J_nu, K)) return m->fail(IRE_E_INVALID, "non-finite J_nu");
+    for (int k = 0; k < K; ++k)
+        if (!(J_nu[k] >= 0.0)) return m->fail(IRE_E_INVALID, "J_nu[%d] < 0", k);
+    m->J.assign(J_nu, J_nu + K);
+    m->dirty = true;
+    m->begun = false;
+    return IRE_OK;
+}
+
+int ire_set_point_source(ire_model *m, double L, const double *spectrum) {
+    if (!m) return IRE_E_INVALID;
+    if (L == 0.0) { m->S.clear(); m->L_ps = 0.0; m->dirty = true; m->begun = false; return IRE_OK; }
+    if (!(L > 0.0) || !std::isfinite(L) || !spectrum) return m->fail(IRE_E_INVALID, "need L > 0 and a spectrum");
+    if (m->nu.empty()) return m->fail(IRE_E_STATE, "set the dust (frequency grid) before the point source");
+    const int K = (int)m->nu.size();
+    if (!finite_all(spectrum, K)) return m->fail(IRE_E_INVALID, "non-finite spectrum");
+    double tot = 0.0;
+    for (int k = 0; k < K; ++k) {
+        if (!(spectrum[k] >= 0.0)) return m->fail(IRE_E_INVALID, "spectrum[%d] < 0", k);
+        tot += spectrum[k];
+    }
+    if (!(tot > 0.0)) return m->fail(IRE_E_INVALID, "spectrum is all zero");
+    m->S.assign(spectrum, spectrum + K);
+    m->L_ps = L;
+    m->dirty = true;
+    m->begun = false;
+    return IRE_OK;
+}
+
+int ire_set_options(ire_model *m, const ire_options *o) {
+    if (!m) return IRE_E_INVALID;
+    if (!o) return m->fail(IRE_E_INVALID, "null options");
+    if (!(o->k_bg > 0.0 && o->k_bg <= 1.0)) return m->fail(IRE_E_INVALID, "k_bg must be in (0,1]");
+    if (!(o->w_floor >= 0.0 && o->w_floor < 1.0)) return m->fail(IRE_E_INVALID, "w_floor must be in [0,1)");
+    if (o->stepping != IRE_FP32 && o->stepping != IRE_FP64) return m->fail(IRE_E_INVALID, "stepping must be IRE_FP32 or IRE_FP64");
+    if (o->max_lanes < 0) return m->fail(IRE_E_INVALID, "max_lanes must be >= 0");
+    if (o->ffi != 0 && o->ffi != 1) return m->fail(IRE_E_INVALID, "ffi must be 0 or 1");
+    if (o->reemit_uniform != 0 && o->reemit_uniform != 1) return m->fail(IRE_E_INVALID, "reemit_uniform must be 0 or 1");
+    if (o->aggregate != 0 && o->aggregate != 1) return m->fail(IRE_E_INVALID, "aggregate must be 0 or 1");
+    if (o->batch < 0 || o->batch > 64) return m->fail(IRE_E_INVALID, "batch must be in [0, 64]");
+    m->opt = *o;
+    return IRE_OK;
+}
+
+int ire_begin(ire_model *m, uint64_t n_ext_total, uint64_t n_ps_total, uint64_t seed) {
+    if (!m) return IRE_E_INVALID;
+    int rc = check_ready(m);
+    if (rc) return rc;
+    if (n_ext_total > 0 && m->J.empty()) return m->fail(IRE_E_STATE, "external packages requested but no external field is set");
+    if (n_ps_total > 0 && m->S.empty()) return m->fail(IRE_E_STATE, "point-source packages requested but no point source is set");
+    hipError_t e;
+    if ((e = hipSetDevice(m->device)) != hipSuccess) return m->hip_fail(e, "hipSetDevice");
+    if (m->dirty) {
+        const auto start = std::chrono::steady_clock::now();
+        rc = build_tables(m);
+        if (rc) return rc;
+        m->ms_tables = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - start).count();
+    }
+    if (n_ext_total > 0 && !(m->L_ext > 0.0)) return m->fail(IRE_E_STATE, "the external field carries no power on this grid");
+    m->n_total[0] = n_ext_total;
+    m->n_total[1] = n_ps_total;
+    m->n_done[0] = m->n_done[1] = 0;
+    m->seed = seed;
+    m->eps[0] = n_ext_total ? m->L_ext / (double)n_ext_total : 0.0;
+    m->eps[1] = n_ps_total ? m->L_ps / (double)n_ps_total : 0.0;
+    m->ms_trace = 0.0f;
+    m->ms_finalize = 0.0f;
+    m->timed = false;
+    if ((e = ire::launch_zero(m->A.p, (int)m->rho.size(), m->stats.p, 1, nullptr)) != hipSuccess)
+        return m->hip_fail(e, "zero accumulators");
+    if ((e = hipStreamSynchronize(nullptr)) != hipSuccess) return m->hip_fail(e, "zero accumulators");
+    m->begun = true;
+    return IRE_OK;
+}
+
+int ire_advance(ire_model *m, uint64_t n_ext, uint64_t n_ps, void *hip_stream) {
+    if (!m) return IRE_E_INVALID;
+    if (!m->begun || m->dirty) return m->fail(IRE_E_STATE, "ire_begin must precede ire_advance (and follow any setter)");
+    if (n_ext > m->n_total[0] - m->n_done[0] || n_ps > m->n_total[1] - m->n_done[1])
+        return m->fail(IRE_E_INVALID, "more packages requested than remain in the run");
+    if (n_ext + n_ps == 0) return IRE_OK;
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    hipError_t e;
+    if ((e = hipSetDevice(m->device)) != hipSuccess) return m->hip_fail(e, "hipSetDevice");
+    const int n = (int)m->rho.size(), K = (int)m->nu.size();
+    const int fp64 = m->opt.stepping == IRE_FP64;
+    size_t lds = 0;
+    int block, grid;
+    if (fp64) {
+        block = 256;
+        grid = m->n_cu * 8;
+    } else {
+        lds = ire::trace_lds_bytes(n, K, m->n_t);
+        if (lds > m->max_lds)
+            return m->fail(IRE_E_INVALID, "FP32 tables need %zu bytes of LDS, the device has %zu; use IRE_FP64",
+                           lds, m->max_lds);
+        if ((e = ire::trace_configure(0, m->opt.aggregate, lds)) != hipSuccess) return m->hip_fail(e, "configure tracer");
+        block = ire::trace_block_fp32();
+        grid = m->n_cu;
+    }
+    if (m->opt.max_lanes > 0) {
+        const int waves = (m->opt.max_lanes + 63) / 64;
+        const int wpb = block / 64;
+        grid = std::min(grid, (waves + wpb - 1) / wpb);
+        if (grid < 1) grid = 1;
+    }
+    ire::TraceParams p{};
+    p.n = n; p.K = K; p.n_t = m->n_t;
+    p.cavity = m->r_edges[0] > 0.0 ? 1 : 0;
+    p.shf = m->shf.p; p.dustf = m->dustf.p; p.cdff = m->cdff.p; p.Gf = m->Gf.p; p.Df = m->Df.p;
+    p.shd = m->shd.p; p.dustd = m->dustd.p; p.cdfd = m->cdfd.p; p.Gd = m->Gd.p; p.Dd = m->Dd.p;
+    p.invM = m->invM.p;
+    p.eps[0] = m->eps[0]; p.eps[1] = m->eps[1];
+    p.n_ext = n_ext; p.n_ps = n_ps;
+    p.pid0[0] = m->n_done[0]; p.pid0[1] = m->n_done[1];
+    p.seed = m->seed;
+    p.k_bg = m->opt.k_bg; p.ffi = m->opt.ffi; p.reemit_uniform = m->opt.reemit_uniform;
+    p.w_floor = m->opt.w_floor; p.max_events = m->opt.max_events; p.max_lanes = m->opt.max_lanes;
+    p.A = m->A.p; p.stats = m->stats.p;
+    {
+        const unsigned long long waves = (unsigned long long)grid * (block / 64);
+        unsigned long long c = (n_ext + n_ps) / (waves * 8ull);
+        p.chunk = std::min<unsigned long long>(std::max<unsigned long long>(c, 64ull), 4096ull);
+    }
+    p.batch = m->opt.batch > 0 ? m->opt.batch : 24;
+    if ((e = ire::launch_zero(nullptr, n, m->stats.p, 0, s)) != hipSuccess) return m->hip_fail(e, "cursor reset");
+    if ((e = hipEventRecord(m->ev0, s)) != hipSuccess) return m->hip_fail(e, "event");
+    if ((e = ire::launch_trace(p, fp64, m->opt.aggregate, grid, block, lds, s)) != hipSuccess)
+        return m->hip_fail(e, "trace launch");
+    if ((e = hipEventRecord(m->ev1, s)) != hipSuccess) return m->hip_fail(e, "event");
+    m->timed = true;
+    m->last_stream = s;
+    m->n_done[0] += n_ext;
+    m->n_done[1] += n_ps;
+    return IRE_OK;
+}
+
+int ire_run(ire_model *m, uint64_t n_ext, uint64_t n_ps, uint64_t seed, void *hip_stream) {
+    int rc = ire_begin(m, n_ext, n_ps, seed);
+    if (rc) return rc;
+    return ire_advance(m, n_ext, n_ps, hip_stream);
+}
+
+int ire_reset(ire_model *m) {
+    if (!m) return IRE_E_INVALID;
+    if (!m->begun) return IRE_OK;
+    return ire_begin(m, m->n_total[0], m->n_total[1], m->seed);
+}
+
+int ire_sync(ire_model *m) {
+    if (!m) return IRE_E_INVALID;
+    hipError_t e;
+    if ((e = hipSetDevice(m->device)) != hipSuccess) return m->hip_fail(e, "hipSetDevice");
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return m->hip_fail(e, "synchronize");
+    return IRE_OK;
+}
+
+static int finalize(ire_model *m, hipStream_t s) {
+    ire::FinalizeParams f{};
+    f.n = (int)m->rho.size();
+    f.n_t = m->n_t;
+    f.A = m->A.p; f.invM = m->invM.p; f.Gd = m->Gd.p; f.lnG = m->lnGd.p; f.lnT = m->lnTd.p;
+    f.t_min = m->t_min; f.t_max = m->t_max;
+    f.A_out = m->A_out.p; f.T_out = m->T_out.p;
+    f.stats = m->stats.p;
+    hipError_t e = ire::launch_finalize(f, s);
+    if (e != hipSuccess) return m->hip_fail(e, "finalize launch");
+    return IRE_OK;
+}
+
+static void fill_stats(const ire_model *m, const ire::DevStats &hs, ire_stats *stats) {
+    if (stats) {
+        stats->L_ext = m->n_total[0] ? m->L_ext : 0.0;
+        stats->L_ps = m->n_total[1] ? m->L_ps : 0.0;
+        stats->escaped[0] = hs.tally[ire::T_ESC_EXT];
+        stats->escaped[1] = hs.tally[ire::T_ESC_PS];
+        stats->ffi_escaped = hs.tally[ire::T_FFI];
+        stats->terminated = hs.tally[ire::T_TERM];
+        stats->n_launch = hs.cnt[ire::C_LAUNCH];
+        stats->n_cross = hs.cnt[ire::C_CROSS];
+        stats->n_scat = hs.cnt[ire::C_SCAT];
+        stats->n_abs = hs.cnt[ire::C_ABS];
+        stats->n_escape = hs.cnt[ire::C_ESCAPE];
+        stats->n_direct = hs.cnt[ire::C_DIRECT];
+        stats->n_limit = hs.cnt[ire::C_LIMIT];
+        stats->n_floor = hs.cnt[ire::C_FLOOR];
+        stats->n_below = hs.cnt[ire::C_BELOW];
+        stats->n_above = hs.cnt[ire::C_ABOVE];
+        stats->n_reemit_above = hs.cnt[ire::C_REEMIT_ABOVE];
+        stats->ms_tables = m->ms_tables;
+        stats->ms_trace = m->ms_trace;
+        stats->ms_finalize = m->ms_finalize;
+    }
+}
+
+int ire_get_results(ire_model *m, double *absorbed, double *T, ire_stats *stats) {
+    if (!m) return IRE_E_INVALID;
+    if (!m->begun) return m->fail(IRE_E_STATE, "no run to report");
+    hipError_t e;
+    if ((e = hipSetDevice(m->device)) != hipSuccess) return m->hip_fail(e, "hipSetDevice");
+    hipStream_t s = m->last_stream;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return m->hip_fail(e, "synchronize");
+    if (m->timed) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, m->ev0, m->ev1) == hipSuccess) m->ms_trace = ms;
+    }
+    // the clamp counters are recomputed by each finalize
+    ire::DevStats hs;
+    if ((e = hipMemcpy(&hs, m->stats.p, sizeof(hs), hipMemcpyDeviceToHost)) != hipSuccess)
+        return m->hip_fail(e, "stats copy");
+    hs.cnt[ire::C_BELOW] = 0;
+    hs.cnt[ire::C_ABOVE] = 0;
+    if ((e = hipMemcpy(m->stats.p, &hs, sizeof(hs), hipMemcpyHostToDevice)) != hipSuccess)
+        return m->hip_fail(e, "stats copy");
+    if ((e = hipEventRecord(m->ev0, s)) != hipSuccess) return m->hip_fail(e, "event");
+    int rc = finalize(m, s);
+    if (rc) return rc;
+    if ((e = hipEventRecord(m->ev1, s)) != hipSuccess) return m->hip_fail(e, "event");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return m->hip_fail(e, "finalize");
+    float msf = 0.0f;
+    if (hipEventElapsedTime(&msf, m->ev0, m->ev1) == hipSuccess) m->ms_finalize = msf;
+    m->timed = false;
+    const size_t n = m->rho.size();
+    if (absorbed && (e = hipMemcpy(absorbed, m->A_out.p, n * sizeof(double), hipMemcpyDeviceToHost)) != hipSuccess)
+        return m->hip_fail(e, "copy absorbed");
+    if (T && (e = hipMemcpy(T, m->T_out.p, n * sizeof(double), hipMemcpyDeviceToHost)) != hipSuccess)
+        return m->hip_fail(e, "copy T");
+    if ((e = hipMemcpy(&hs, m->stats.p, sizeof(hs), hipMemcpyDeviceToHost)) != hipSuccess)
+        return m->hip_fail(e, "stats copy");
+    fill_stats(m, hs, stats);
+    if (hs.cnt[ire::C_LIMIT] > 0) return m->fail(IRE_E_LIMIT, "%llu packages reached max_events", hs.cnt[ire::C_LIMIT]);
+    return IRE_OK;
+}
+
+int ire_get_stats(ire_model *m, ire_stats *stats) {
+    if (!m) return IRE_E_INVALID;
+    if (!m->begun) return m->fail(IRE_E_STATE, "no run to report");
+    hipError_t e;
+    if ((e = hipSetDevice(m->device)) != hipSuccess) return m->hip_fail(e, "hipSetDevice");
+    if ((e = hipStreamSynchronize(m->last_stream)) != hipSuccess) return m->hip_fail(e, "synchronize");
+    if (m->timed) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, m->ev0, m->ev1) == hipSuccess) m->ms_trace = ms;
+    }
+    ire::DevStats hs;
+    if ((e = hipMemcpy(&hs, m->stats.p, sizeof(hs), hipMemcpyDeviceToHost)) != hipSuccess)
+        return m->hip_fail(e, "stats copy");
+    fill_stats(m, hs, stats);
+    return IRE_OK;
+}
+
+int ire_get_results_dev(ire_model *m, double *absorbed_dev, double *T_dev, void *hip_stream) {
+    if (!m) return IRE_E_INVALID;
+    if (!m->begun) return m->fail(IRE_E_STATE, "no run to report");
+    hipError_t e;
+    if ((e = hipSetDevice(m->device)) != hipSuccess) return m->hip_fail(e, "hipSetDevice");
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    ire::FinalizeParams f{};
+    f.n = (int)m->rho.size();
+    f.n_t = m->n_t;
+    f.A = m->A.p; f.invM = m->invM.p; f.Gd = m->Gd.p; f.lnG = m->lnGd.p; f.lnT = m->lnTd.p;
+    f.t_min = m->t_min; f.t_max = m->t_max;
+    f.A_out = absorbed_dev ? absorbed_dev : m->A_out.p;
+    f.T_out = T_dev ? T_dev : m->T_out.p;
+    f.stats = m->stats.p;
+    if ((e = ire::launch_finalize(f, s)) != hipSuccess) return m->hip_fail(e, "finalize launch");
+    return IRE_OK;
+}
+
+int ire_planck(int32_t K, const double *nu, double T, double *out) {
+    if (K < 1 || !nu || !out || !std::isfinite(T)) return IRE_E_INVALID;
+    for (int k = 0; k < K; ++k) out[k] = planck(nu[k], T);
+    return IRE_OK;
+}
+
+}  // extern "C"

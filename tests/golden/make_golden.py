@@ -1,0 +1,52 @@
+"""Write the oracle ensembles the GPU parity tests compare against.
+
+Calls only the oracle (and the seeded workload generator): 16 independent
+seeds per configuration, per-shell mean and standard deviation of T and A.
+Usage: python tests/golden/make_golden.py [name ...]
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_2408_13807_amd import workloads as wl  # noqa: E402
+
+CASES = {
+    # name: (workload factory, packages per source, options)
+    "ext50_tau1_1e5": (wl.cfg_external_small, dict(n_ext=100_000), {}),
+    "ext101_tau10_1e6": (wl.cfg_external_large, dict(n_ext=1_000_000), {}),
+    "ext101_tau10_1e7": (wl.cfg_external_large, dict(n_ext=10_000_000), {}),
+    "ext101_tau10_kbg_ffi_1e6": (wl.cfg_external_large, dict(n_ext=1_000_000), dict(k_bg=0.2, ffi=1)),
+    "central200_tau100_1e6": (wl.cfg_central, dict(n_ps=1_000_000), {}),
+    "central200_tau100_1e7": (wl.cfg_central, dict(n_ps=10_000_000), {}),
+}
+
+
+def make(name: str) -> str:
+    factory, npk, opts = CASES[name]
+    m = factory()
+    t0 = time.time()
+    e = oracle.ensemble(m, seeds=range(1, 17), **npk, **opts)
+    out = dict(name=name, workload=factory.__name__, packages=npk, options=opts, seeds=list(range(1, 17)),
+               T_mean=e["T"].mean(axis=0).tolist(), T_std=e["T"].std(axis=0, ddof=1).tolist(),
+               A_mean=e["A"].mean(axis=0).tolist(), A_std=e["A"].std(axis=0, ddof=1).tolist(),
+               n_cross=float(np.mean([s["n_cross"] for s in e["stats"]])),
+               n_abs=float(np.mean([s["n_abs"] for s in e["stats"]])),
+               n_scat=float(np.mean([s["n_scat"] for s in e["stats"]])),
+               oracle_seconds=time.time() - t0)
+    path = os.path.join(HERE, f"{name}.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    return path
+
+
+if __name__ == "__main__":
+    for n in sys.argv[1:] or list(CASES):
+        print(make(n), flush=True)

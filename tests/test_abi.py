@@ -1,0 +1,61 @@
+"""The C-ABI library loads and exports every entry point include/ire.h declares
+(host-only checks: nothing here launches GPU work)."""
+import ctypes as ct
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared(header):
+    text = open(os.path.join(ROOT, "include", header)).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b((?:ire|sur)_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2408_13807_amd import ire
+    lib = ire.library()
+    names = declared("ire.h")
+    assert len(names) >= 18
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(ire.EXPORTS) == names
+
+
+def test_options_layout_and_defaults():
+    from paper_2408_13807_amd import ire
+    o = ire.default_options()
+    assert (o.k_bg, o.ffi, o.w_floor, o.max_events, o.stepping, o.max_lanes, o.reemit_uniform,
+            o.aggregate, o.batch) == (0.5, 0, 1e-10, 1000000, 0, 0, 0, 1, 0)
+
+
+def test_planck_helper_matches_oracle(orc):
+    from paper_2408_13807_amd import ire
+    nu = np.geomspace(1e10, 1e16, 50)
+    for T in (3.0, 20.0, 5000.0):
+        got = ire.planck(nu, T)
+        want = np.array([orc.planck(x, T) for x in nu])
+        np.testing.assert_allclose(got, want, rtol=1e-13, atol=0)
+
+
+def test_create_without_gpu_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_2408_13807_amd import ire
+    with pytest.raises(ire.IREError) as e:
+        ire.IREModel(0)
+    assert e.value.code == ire.IRE_E_DEVICE
+
+
+def test_null_handle_calls_are_safe():
+    from paper_2408_13807_amd import ire
+    lib = ire.library()
+    lib.ire_destroy(None)
+    assert lib.ire_set_options(None, None) == ire.IRE_E_INVALID
+    assert lib.ire_run(None, 1, 0, 1, None) == ire.IRE_E_INVALID
+    assert lib.ire_last_error(None) == b"null handle"
