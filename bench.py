@@ -91,7 +91,7 @@ def main() -> int:
 
     h = ire.IREModel(0)
     h.set_model(model)
-    h.set_options()
+    h.set_options(batch=int(os.environ.get("IRE_BENCH_BATCH", "0")))
 
     def step(seed: int):
         h.run(seed=seed, stream=stream, **{key: n_pkg})

@@ -56,7 +56,7 @@ typedef struct ire_options {
     int32_t reemit_uniform; /* Sect. 4: re-emit at a uniformly random point of the shell volume (0/1) */
     int32_t aggregate;    /* 1: wave-level reduction of absorbed energy before the global atomic; 0: one atomic per lane */
     int32_t batch;        /* lanes of a wave parked at an event before their events are processed together
-                             (1..64; 0 = default 24); changes speed, not the distribution of results */
+                             (1..64; 0 = default 32); changes speed, not the distribution of results */
 } ire_options;
 
 typedef struct ire_stats {
@@ -141,6 +141,128 @@ const char *ire_last_error(const ire_model *m);
 
 /* Planck function B_nu(T) on nu[K] into out[K] (host helper). */
 int ire_planck(int32_t K, const double *nu, double T, double *out);
+
+/* ------------------------------------------------------------------------
+ * Batched parameter studies: many cloud models in one persistent launch.
+ * The models share the dust, the temperature grid and the source spectral
+ * shapes; each has its own shells, source type and strength, package budget
+ * and seed.  The method per model is the one above (Sect. 2.1-2.2); batching
+ * is a scheduling device for the parameter studies the paper has in view
+ * (Abstract, Sect. 5).  FP32 path stepping, FP64 accumulators.
+ */
+
+#define IRE_SRC_EXTERNAL 0
+#define IRE_SRC_POINT 1
+
+typedef struct ire_batch ire_batch;
+
+typedef struct ire_model_desc {
+    int32_t n_shells;     /* shells of this model; its r_edges hold n_shells + 1 values */
+    int32_t source;       /* IRE_SRC_EXTERNAL or IRE_SRC_POINT */
+    double scale;         /* external: multiplier of the batch's J_nu shape; point: luminosity L (erg/s) */
+    uint64_t n_packages;  /* packages of this model (>= 1) */
+    uint64_t seed;        /* random stream of this model */
+} ire_model_desc;
+
+typedef struct ire_batch_options {
+    double k_bg;              /* as ire_options */
+    int32_t ffi;
+    double w_floor;
+    uint64_t max_events;
+    int32_t reemit_uniform;
+    int32_t aggregate;
+    int32_t batch;            /* lanes parked at an event before the wave processes events (0 = 32) */
+    uint64_t item_packages;   /* packages per work item; a model is split into items (0 = 65536) */
+    int32_t use_graph;        /* 1: replay zero/trace/finalize as a captured HIP graph (default) */
+} ire_batch_options;
+
+typedef struct ire_batch_stats {
+    double L_total;            /* sum of the models' source luminosities (erg/s) */
+    double escaped, ffi_escaped, terminated;
+    uint64_t n_launch, n_cross, n_scat, n_abs, n_escape, n_limit, n_floor, n_below, n_above;
+    uint64_t n_models, n_items, n_shells;
+    float ms_run;              /* zero + trace + finalize on the device (HIP events) */
+} ire_batch_stats;
+
+/* Defaults: as ire_default_options, item_packages 65536, use_graph 1. */
+int ire_batch_default_options(ire_batch_options *o);
+int ire_batch_create(int hip_device, ire_batch **out);
+void ire_batch_destroy(ire_batch *b);
+/* As ire_set_dust / ire_set_temperature_grid, shared by every model of the batch. */
+int ire_batch_set_dust(ire_batch *b, int32_t K, const double *nu, const double *kappa_abs,
+                       const double *albedo, const double *g);
+int ire_batch_set_temperature_grid(ire_batch *b, double t_min, double t_max, int32_t n_t);
+/* Spectral shapes on the dust grid: J_shape[K] for external models (NULL if
+ * none), S_shape[K] for point-source models (NULL if none); copied. */
+int ire_batch_set_sources(ire_batch *b, const double *J_shape, const double *S_shape);
+/* M models; r_edges_flat holds sum(n_shells + 1) radii and rho_flat sum(n_shells)
+ * densities, model after model, with the constraints of ire_set_shells. */
+int ire_batch_set_models(ire_batch *b, int32_t M, const ire_model_desc *models,
+                         const double *r_edges_flat, const double *rho_flat);
+int ire_batch_set_options(ire_batch *b, const ire_batch_options *o);
+/* Run every model from zero absorbed energy (asynchronous on hip_stream). */
+int ire_batch_run(ire_batch *b, void *hip_stream);
+/* Synchronise and copy A_flat[sum n_shells] (erg/s) and T_flat (K); either may be NULL. */
+int ire_batch_get(ire_batch *b, double *A_flat, double *T_flat, ire_batch_stats *stats);
+/* Time candidate schedules (parking threshold x item size) on a sample of the
+ * models with package budgets scaled by `fraction` (0 < fraction <= 1), keep
+ * the fastest in the batch options and in *chosen (may be NULL).  With a
+ * cache_path, a previous choice for the same device and model class is reused
+ * and new choices are stored (JSON). */
+int ire_batch_autotune(ire_batch *b, double fraction, const char *cache_path, ire_batch_options *chosen);
+const char *ire_batch_last_error(const ire_batch *b);
+
+/* ------------------------------------------------------------------------
+ * Learned surrogate of the IRE temperature profile: an ensemble of MLPs
+ * mapping 6 inputs (log10 tau_V, density exponent, log10 L/L_sun or 0,
+ * log10 external-field scale or 0, source type 0/1, r_mid/R_out) through
+ * `depth` hidden layers of width 256 (SiLU) to log10 T of a shell.  BF16
+ * weights and matrix-core (MFMA) products with FP32 accumulation; FP32 master
+ * weights and Adam.  Trained on temperatures from the IRE tracer, which also
+ * serves as the fallback wherever the ensemble's spread is too large.
+ */
+
+typedef struct sur_net sur_net;
+
+typedef struct sur_train_opts {
+    int64_t batch;       /* rows per member and step (default 4096, multiple of 128) */
+    int64_t steps;       /* optimizer steps (default 2000) */
+    double lr, lr_min;   /* cosine learning-rate schedule from lr to lr_min (1e-3, 1e-5) */
+    double beta1, beta2, eps;  /* Adam (0.9, 0.999, 1e-8) */
+    uint64_t seed;       /* mini-batch sampling (rows drawn with replacement) */
+    int32_t use_graph;   /* 1: capture one step as a HIP graph and replay it (default) */
+} sur_train_opts;
+
+int sur_default_train_opts(sur_train_opts *o);
+/* members >= 1 ensemble members, width must be 256, depth >= 1 hidden layers;
+ * weights initialised from `seed` (He-uniform, zero biases). */
+int sur_create(int hip_device, int32_t members, int32_t width, int32_t depth, uint64_t seed, sur_net **out);
+void sur_destroy(sur_net *s);
+/* Input standardisation x' = (x - mean) / std (6 values each) and target
+ * log10 T = y_mean + y_std * output.  sur_train sets them from its data when
+ * they were never set. */
+int sur_set_normalization(sur_net *s, const float *x_mean, const float *x_std, float y_mean, float y_std);
+/* Parameters per member (FP32, the flat layout of the weights, biases, output weights). */
+int64_t sur_param_count(const sur_net *s);
+int sur_get_params(sur_net *s, float *params /* members * sur_param_count */);
+int sur_set_params(sur_net *s, const float *params);
+/* Train every member on rows X[n][6] (host), targets log10 T y[n] (host). */
+int sur_train(sur_net *s, const float *X, const float *y, int64_t n, const sur_train_opts *o, void *hip_stream,
+              float *final_loss /* members, may be NULL */);
+/* Loss (mean squared error of the standardised target) and its gradient with
+ * respect to every parameter for exactly these rows (1 <= n <= 65536), every
+ * member, without an update (gradient checks). */
+int sur_gradients(sur_net *s, const float *X, const float *y, int64_t n, float *grads /* members * count */,
+                  float *loss /* members */);
+/* Ensemble prediction: mean over members of log10 T and the relative spread
+ * std(T)/mean(T) per row (host arrays). */
+int sur_predict(sur_net *s, const float *X, int64_t n, float *mean_logT, float *spread);
+/* Same on device pointers, asynchronous on hip_stream. */
+int sur_predict_dev(sur_net *s, const float *X_dev, int64_t n, float *mean_logT_dev, float *spread_dev,
+                    void *hip_stream);
+int sur_save(sur_net *s, const char *path);
+int sur_load(sur_net *s, const char *path);
+const char *sur_last_error(const sur_net *s);
 
 #ifdef __cplusplus
 }

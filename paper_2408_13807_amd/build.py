@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIB_DIR, "libire.so")
 
-SOURCES = ["ire_trace.hip", "ire_api.cpp"]
+SOURCES = ["ire_trace.hip", "ire_api.cpp", "ire_batch.cpp", "sur_kernels.hip", "sur_api.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -12,65 +12,16 @@
 #include <vector>
 
 #include "ire.h"
+#include "ire_host.h"
 #include "ire_internal.h"
 
 namespace ire {
 int trace_block_fp32();
 }
 
-namespace {
-
-constexpr double kH = 6.62607015e-27;   // erg s
-constexpr double kKB = 1.380649e-16;    // erg / K
-constexpr double kC = 2.99792458e10;    // cm / s
-constexpr double kPi = 3.14159265358979323846;
-
-// Planck intensity B_nu(T); 0 for T <= 0 and where exp(h nu / kT) overflows.
-double planck(double nu, double T) {
-    if (!(T > 0.0)) return 0.0;
-    const double x = kH * nu / (kKB * T);
-    if (x > 700.0) return 0.0;
-    return (2.0 * kH / (kC * kC)) * nu * nu * nu / std::expm1(x);
-}
-
-// Normalised cumulative sums of q into out (the last entry exactly 1).
-void cumulative(const double *q, int K, double *out) {
-    double total = 0.0;
-    for (int k = 0; k < K; ++k) total += q[k];
-    double run = 0.0;
-    for (int k = 0; k < K; ++k) {
-        run += q[k];
-        out[k] = total > 0.0 ? run / total : 1.0;
-    }
-    out[K - 1] = 1.0;
-}
-
-template <typename T>
-struct DevBuf {
-    T *p = nullptr;
-    size_t n = 0;
-    hipError_t ensure(size_t count) {
-        if (count <= n && p) return hipSuccess;
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        n = 0;
-        hipError_t e = hipMalloc(reinterpret_cast<void **>(&p), std::max<size_t>(count, 1) * sizeof(T));
-        if (e == hipSuccess) n = count;
-        return e;
-    }
-    hipError_t upload(const std::vector<T> &h) {
-        hipError_t e = ensure(h.size());
-        if (e != hipSuccess) return e;
-        return hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
-    }
-    void release() {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        n = 0;
-    }
-};
-
-}  // namespace
+using ire::host::DevBuf;
+using ire::host::finite_all;
+using ire::host::kPi;
 
 struct ire_model {
     int device = 0;
@@ -126,93 +77,37 @@ struct ire_model {
 
 namespace {
 
-bool finite_all(const double *a, size_t n) {
-    for (size_t j = 0; j < n; ++j)
-        if (!std::isfinite(a[j])) return false;
-    return true;
-}
-
 // Build every table in FP64 on the host and upload FP32 and FP64 copies.
 int build_tables(ire_model *m) {
     const int n = (int)m->rho.size();
     const int K = (int)m->nu.size();
-    const int nt = m->n_t;
     const double Rout = m->r_edges[n];
+    ire::host::DustTables dt;
+    const std::string err = ire::host::build_dust_tables(m->nu, m->kabs, m->albedo, m->g, m->t_min, m->t_max,
+                                                         m->n_t, dt);
+    if (!err.empty()) return m->fail(IRE_E_INVALID, "%s", err.c_str());
+    std::vector<ire::ShellF> shf;
+    std::vector<ire::ShellD> shd;
+    std::vector<double> invM;
+    ire::host::build_shell_table(m->r_edges.data(), m->rho.data(), n, shf, shd, invM);
+    const std::vector<ire::DustF> &df = dt.df;
+    const std::vector<ire::DustD> &dd = dt.dd;
+    const std::vector<double> &G = dt.G, &D = dt.D, &w = dt.w;
 
-    // trapezoid weights in linear frequency
-    std::vector<double> w(K);
-    if (K == 1) {
-        w[0] = 1.0;
-    } else {
-        for (int k = 0; k < K; ++k) {
-            const double left = k > 0 ? m->nu[k] - m->nu[k - 1] : 0.0;
-            const double right = k + 1 < K ? m->nu[k + 1] - m->nu[k] : 0.0;
-            w[k] = 0.5 * (left + right);
-        }
-    }
-
-    // shells
-    std::vector<ire::ShellF> shf(n);
-    std::vector<ire::ShellD> shd(n);
-    std::vector<double> invM(n);
-    for (int i = 0; i < n; ++i) {
-        const double a = m->r_edges[i] / Rout, b = m->r_edges[i + 1] / Rout;
-        shd[i] = ire::ShellD{a * a, b * b, m->rho[i] * Rout, a};
-        shf[i] = ire::ShellF{(float)(a * a), (float)(b * b), (float)(m->rho[i] * Rout), (float)a};
-        const double r0 = m->r_edges[i], r1 = m->r_edges[i + 1];
-        const double M = m->rho[i] * (4.0 * kPi / 3.0) * (r1 * r1 * r1 - r0 * r0 * r0);
-        invM[i] = M > 0.0 ? 1.0 / M : 0.0;
-    }
-    // the outermost edge is exactly 1 in both precisions
-    shd[n - 1].r2_out = 1.0;
-    shf[n - 1].r2_out = 1.0f;
-
-    // dust
-    std::vector<ire::DustF> df(K);
-    std::vector<ire::DustD> dd(K);
-    for (int k = 0; k < K; ++k) {
-        const double kS = m->kabs[k] * m->albedo[k] / (1.0 - m->albedo[k]);
-        dd[k] = ire::DustD{m->kabs[k], kS, m->g[k], m->albedo[k]};
-        df[k] = ire::DustF{(float)m->kabs[k], (float)kS, (float)m->g[k], (float)m->albedo[k]};
-    }
-
-    // sources: frequency CDFs of J w and S w
+    // sources: frequency CDFs of J w and S w; the external luminosity is the
+    // inward flux pi J through the surface
     std::vector<double> q(K), cdf(2 * K);
     double sumJ = 0.0;
     for (int k = 0; k < K; ++k) {
         q[k] = m->J.empty() ? 0.0 : m->J[k] * w[k];
         sumJ += q[k];
     }
-    cumulative(q.data(), K, cdf.data());
+    ire::host::cumulative(q.data(), K, cdf.data());
     for (int k = 0; k < K; ++k) q[k] = m->S.empty() ? 0.0 : m->S[k] * w[k];
-    cumulative(q.data(), K, cdf.data() + K);
+    ire::host::cumulative(q.data(), K, cdf.data() + K);
     m->L_ext = 4.0 * kPi * Rout * Rout * kPi * sumJ;
-
-    // temperature grid, G(T) = 4 pi sum kappa_abs B w, and the re-emission rows:
-    // row 0 holds kappa_abs B(T_0) w (absorbed power below the first point),
-    // row j >= 1 holds kappa_abs [B(T_j) - B(T_{j-1})] w
-    std::vector<double> Tg(nt), G(nt), D((size_t)nt * K);
-    m->lnT.assign(nt, 0.0);
-    m->lnG.assign(nt, 0.0);
-    std::vector<double> Bprev(K, 0.0), Bcur(K);
-    for (int j = 0; j < nt; ++j) {
-        Tg[j] = m->t_min * std::pow(m->t_max / m->t_min, (double)j / (double)(nt - 1));
-        double acc = 0.0;
-        for (int k = 0; k < K; ++k) {
-            Bcur[k] = planck(m->nu[k], Tg[j]);
-            acc += m->kabs[k] * Bcur[k] * w[k];
-            q[k] = m->kabs[k] * (Bcur[k] - (j == 0 ? 0.0 : Bprev[k])) * w[k];
-        }
-        G[j] = 4.0 * kPi * acc;
-        m->lnT[j] = std::log(Tg[j]);
-        m->lnG[j] = std::log(G[j]);
-        cumulative(q.data(), K, D.data() + (size_t)j * K);
-        Bprev.swap(Bcur);
-    }
-    for (int j = 1; j < nt; ++j)
-        if (!(G[j] > G[j - 1]))
-            return m->fail(IRE_E_INVALID, "G(T) is not increasing on the temperature grid at point %d", j);
-    if (!(G[0] > 0.0)) return m->fail(IRE_E_INVALID, "G(t_min) underflows: raise t_min");
+    m->lnT = dt.lnT;
+    m->lnG = dt.lnG;
 
     std::vector<float> cdff(cdf.begin(), cdf.end()), Gf(G.begin(), G.end()), Df(D.begin(), D.end());
     hipError_t e;
@@ -456,7 +351,7 @@ int ire_advance(ire_model *m, uint64_t n_ext, uint64_t n_ps, void *hip_stream) {
         block = 256;
         grid = m->n_cu * 8;
     } else {
-        lds = ire::trace_lds_bytes(n, K, m->n_t);
+        lds = ire::trace_lds_bytes(n + (m->r_edges[0] > 0.0 ? 1 : 0) + 1, K, m->n_t);
         if (lds > m->max_lds)
             return m->fail(IRE_E_INVALID, "FP32 tables need %zu bytes of LDS, the device has %zu; use IRE_FP64",
                            lds, m->max_lds);
@@ -488,7 +383,7 @@ int ire_advance(ire_model *m, uint64_t n_ext, uint64_t n_ps, void *hip_stream) {
         unsigned long long c = (n_ext + n_ps) / (waves * 8ull);
         p.chunk = std::min<unsigned long long>(std::max<unsigned long long>(c, 64ull), 4096ull);
     }
-    p.batch = m->opt.batch > 0 ? m->opt.batch : 24;
+    p.batch = m->opt.batch > 0 ? m->opt.batch : 32;
     if ((e = ire::launch_zero(nullptr, n, m->stats.p, 0, s)) != hipSuccess) return m->hip_fail(e, "cursor reset");
     if ((e = hipEventRecord(m->ev0, s)) != hipSuccess) return m->hip_fail(e, "event");
     if ((e = ire::launch_trace(p, fp64, m->opt.aggregate, grid, block, lds, s)) != hipSuccess)
@@ -635,7 +530,7 @@ int ire_get_results_dev(ire_model *m, double *absorbed_dev, double *T_dev, void 
 
 int ire_planck(int32_t K, const double *nu, double T, double *out) {
     if (K < 1 || !nu || !out || !std::isfinite(T)) return IRE_E_INVALID;
-    for (int k = 0; k < K; ++k) out[k] = planck(nu[k], T);
+    for (int k = 0; k < K; ++k) out[k] = ire::host::planck(nu[k], T);
     return IRE_OK;
 }
 

@@ -11,14 +11,15 @@ namespace ire {
 constexpr int kAccStride = 16;
 
 // Shell geometry in units of the outer radius: squared inner and outer radius,
-// and density times the outer radius, so kappa * rho_hat * l_hat is an optical
-// depth when l_hat is a length in outer radii.
-struct ShellF { float r2_in, r2_out, rho, r_in; };
-struct ShellD { double r2_in, r2_out, rho, r_in; };
+// density times the outer radius (so kappa * rho_hat * l_hat is an optical depth
+// when l_hat is a length in outer radii) and its reciprocal (0 for an empty shell).
+struct ShellF { float r2_in, r2_out, rho, inv_rho; };
+struct ShellD { double r2_in, r2_out, rho, inv_rho; };
 
-// Per-frequency dust coefficients: kappa_abs, kappa_sca, HG g, albedo.
-struct DustF { float kA, kS, g, alb; };
-struct DustD { double kA, kS, g, alb; };
+// Per-frequency dust coefficients: kappa_abs and kappa_sca, their reciprocals
+// (infinite for kappa_sca = 0), HG g, albedo, extinction kappa_abs + kappa_sca.
+struct DustF { float kA, kS, inv_kA, inv_kS, g, alb, kext, pad; };
+struct DustD { double kA, kS, inv_kA, inv_kS, g, alb, kext, pad; };
 
 enum Counter {
     C_LAUNCH, C_CROSS, C_SCAT, C_ABS, C_ESCAPE, C_DIRECT, C_LIMIT, C_FLOOR,
@@ -37,7 +38,7 @@ struct TraceParams {
     int n, K, n_t;
     int cavity;                       // 1 if r_edges[0] > 0 (empty central cavity)
     // FP32 tables in global memory (staged into LDS by each workgroup)
-    const ShellF *shf;
+    const ShellF *shf;                // cavity + n + 1: [empty cavity], shells, sentinel beyond the surface
     const DustF *dustf;
     const float *cdff;                // 2*K: source CDFs, external then point source
     const float *Gf;                  // n_t: emitted power per mass on the T grid
@@ -76,11 +77,57 @@ struct FinalizeParams {
     DevStats *stats;
 };
 
-size_t trace_lds_bytes(int n, int K, int n_t);
+// ---- batched launch: many cloud models sharing the dust and temperature tables
+
+struct BatchModelDev {
+    int shell_off;                    // first entry of the model's shell table ([cavity] + n + sentinel)
+    int n, cav, src;                  // shells, cavity flag, source (0 external, 1 point)
+    int acc_off;                      // first shell of the model in the flat per-shell arrays
+    int pad;
+    double eps;                       // package energy
+    unsigned long long n_pkg, seed;
+};
+
+struct BatchItemDev {                 // a range of one model's packages
+    int model, pad;
+    unsigned long long first, count;
+};
+
+struct BatchParams {
+    int K, n_t, n_items, max_table;   // max_table: largest per-model shell table
+    const ShellF *shells;             // all models' shell tables
+    const DustF *dustf;
+    const float *cdff;                // 2*K source CDFs (external field, point source)
+    const float *Gf, *Df;
+    const double *invM;               // per shell, flat
+    double *A;                        // per shell, flat, stride kAccStride
+    const BatchModelDev *models;
+    const BatchItemDev *items;
+    double k_bg;
+    int ffi, reemit_uniform, batch, pad;
+    double w_floor;
+    unsigned long long max_events;
+    DevStats *stats;                  // stats->cursor counts taken items
+};
+
+struct BatchFinalizeParams {
+    int n_shells, n_t;
+    const double *A, *invM, *Gd, *lnG, *lnT;
+    double t_min, t_max;
+    double *A_out, *T_out;
+    DevStats *stats;
+};
+
+size_t trace_lds_bytes(int n_table, int K, int n_t);  // n_table = cavity + n + 1
 hipError_t launch_trace(const TraceParams &p, int fp64, int aggregate, int grid, int block,
                         size_t lds, hipStream_t s);
 hipError_t trace_configure(int fp64, int aggregate, size_t lds);
 hipError_t launch_zero(double *A, int n, DevStats *st, int clear_counts, hipStream_t s);
 hipError_t launch_finalize(const FinalizeParams &p, hipStream_t s);
+hipError_t batch_configure(int aggregate, size_t lds);
+hipError_t launch_trace_batch(const BatchParams &p, int aggregate, int grid, size_t lds, hipStream_t s);
+hipError_t launch_zero_batch(double *A, size_t n_shells, DevStats *st, hipStream_t s);
+hipError_t launch_finalize_batch(const BatchFinalizeParams &p, hipStream_t s);
+int trace_block_fp32();
 
 }  // namespace ire

@@ -1,8 +1,8 @@
 // IRE photon-package tracer for gfx950 (MI355X).
 //
 // One lane follows one package at a time in a persistent wavefront; a lane
-// whose package has left the cloud takes the next package index from a global
-// cursor (one atomic per wave per refill).  Shell geometry is one-dimensional:
+// whose package has left the cloud takes the next package index from a
+// wave-private pool that is refilled from a global cursor in chunks.  Shell geometry is one-dimensional:
 // a straight flight is described by its squared impact parameter b2 (constant)
 // and the signed distance t from the tangent point (r^2 = b2 + t^2), in units
 // of the outer radius.  The shell index changes only by +-1 at a crossing and is
@@ -76,6 +76,11 @@ template <typename R> struct P;
 template <> struct P<float> {
     using Shell = ShellF;
     using Dust = DustF;
+    // one 128-bit load of a shell record
+    static __device__ __forceinline__ ShellF shell(const ShellF *q) {
+        const float4 v = *reinterpret_cast<const float4 *>(q);
+        return ShellF{v.x, v.y, v.z, v.w};
+    }
     static __device__ __forceinline__ float uni(uint32_t x) {
         float u = __builtin_fmaf((float)x, 0x1p-32f, 0x1p-33f);
         return u < 0x1.fffffep-1f ? u : 0x1.fffffep-1f;
@@ -94,6 +99,7 @@ template <> struct P<float> {
 template <> struct P<double> {
     using Shell = ShellD;
     using Dust = DustD;
+    static __device__ __forceinline__ ShellD shell(const ShellD *q) { return *q; }
     static __device__ __forceinline__ double uni(uint32_t x) { return ((double)x + 0.5) * 0x1p-32; }
     static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
     static __device__ __forceinline__ double nlog(double u) { return -log(u); }
@@ -183,113 +189,151 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
 // ---------------------------------------------------------------------------
 // The tracer
 
+// Per-lane event counters and energy tallies (flushed once per wave).
+struct LaneCounters {
+    uint32_t launch = 0, cross = 0, scat = 0, abs = 0, escape = 0, direct = 0, limit = 0, floor = 0,
+             reabove = 0;
+    double esc0 = 0.0, esc1 = 0.0, ffi = 0.0, term = 0.0;
+};
+
+// One cloud model as the tracer sees it.
+template <typename R>
+struct ModelCtx {
+    const typename P<R>::Shell *sh;  // [empty cavity] + n shells + sentinel beyond the surface
+    int n, cav;
+    const double *invM;              // n: 1 / shell mass
+    double *A;                       // n absorbed-energy accumulators, stride kAccStride
+    double eps[2];                   // package energy per source
+    unsigned long long n_ext, n_ps;  // packages to trace per source
+    unsigned long long pid0[2];      // first package id per source
+    unsigned long long seed;
+};
+
+// Method options shared by every model of a launch.
+struct MethodOpts {
+    double k_bg;
+    int ffi, reemit_uniform, batch;
+    double w_floor;
+    unsigned long long max_events;
+};
+
+// Trace every package of one model with the lanes of this wave.  Package
+// indices come from `cursor` (global or LDS memory) `chunk` at a time; the
+// call returns when the cursor is exhausted and every lane is idle.
 template <typename R, bool AGG>
-__device__ __forceinline__ void trace_body(const TraceParams &p, const typename P<R>::Shell *sh,
-                                           const typename P<R>::Dust *dust, const R *cdf,
-                                           const R *G, const R *D) {
+__device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodOpts &o,
+                                            const typename P<R>::Dust *dust, const R *cdf,
+                                            const R *G, const R *D, int K, int n_t,
+                                            unsigned long long *cursor, unsigned long long chunk,
+                                            bool lane_off, LaneCounters &lc) {
     using Shell = typename P<R>::Shell;
     using Dust = typename P<R>::Dust;
-    enum : int { ST_FLY = 0, ST_ABS = 1, ST_SCAT = 2, ST_DEAD = 3 };
-    const int n = p.n, K = p.K, n_t = p.n_t;
-    const uint32_t key0 = (uint32_t)p.seed, key1 = (uint32_t)(p.seed >> 32);
-    const unsigned long long total = p.n_ext + p.n_ps;
+    // lane status: in flight, parked at an interaction (or at the surface),
+    // without a package, finished (no packages left)
+    enum : int { ST_FLY = 0, ST_EVT = 1, ST_DEAD = 3, ST_DONE = 4 };
+    // Shell table: [empty cavity] + the n shells + a sentinel beyond the surface.
+    // A flight that leaves the cloud enters the sentinel, whose infinite density
+    // ends the flight there; the event pass recognises it as an escape.
+    const Shell *const sh = mc.sh;
+    const int cav = mc.cav;
+    const int n_int = mc.n + cav;
+    const uint32_t key0 = (uint32_t)mc.seed, key1 = (uint32_t)(mc.seed >> 32);
+    const unsigned long long total = mc.n_ext + mc.n_ps;
     const int lane = __lane_id();
-    const long long gtid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int batch = p.batch > 0 ? p.batch : 1;
+    const int batch = o.batch > 0 ? o.batch : 1;
+    const Shell *const sentinel = sh + n_int;
 
     unsigned long long pool_next = 0, pool_end = 0;  // wave-uniform
 
     // package state
-    int st = ST_DEAD;
-    bool done = (p.max_lanes > 0) && (gtid >= p.max_lanes);
-    int i = 0, k = 0, src = 0;
-    R b2 = 0, t = 0, tauA = 0, tauS = 0, W = 1, W0 = 1;
-    R kA = 0, kS = 0, gg = 0, alb = 0;
+    int st = lane_off ? ST_DONE : ST_DEAD;
+    const Shell *ps = sh;   // current shell
+    int k = 0, src = 0;
+    R b2 = 0, t = 0, W = 1, W0 = 1;
+    R sig = 0;          // column (rho-weighted length) left before the next interaction
+    double eps = 0.0;   // package energy of the lane's source
+    bool ev_abs = false; // that interaction is an absorption (else a scattering)
     uint32_t pid_lo = 0, pid_hi = 0, blk = 0;
     unsigned long long events = 0;
 
-    // per-lane counters and tallies
-    uint32_t c_launch = 0, c_cross = 0, c_scat = 0, c_abs = 0, c_escape = 0, c_direct = 0;
-    uint32_t c_limit = 0, c_floor = 0, c_reabove = 0;
-    double esc0 = 0.0, esc1 = 0.0, ffi_esc = 0.0, term = 0.0;
-
-    auto escape = [&]() {
-        const double e = p.eps[src] * (double)W;
-        if (src == 0) esc0 += e; else esc1 += e;
-        c_escape++;
-        if (events == 0) c_direct++;
-        st = ST_DEAD;
-    };
-
     for (;;) {
-        // ---- crossing sweep: lanes in flight step from boundary to boundary;
-        // a lane that reaches an event (or loses its package) parks until
-        // enough lanes of the wave are parked to process their events together
-        for (;;) {
-            const unsigned long long fly = __ballot(st == ST_FLY);
-            const unsigned long long wait = __ballot(st != ST_FLY && !done);
-            const int live = __popcll(fly | wait);
-            const int want = batch < (live + 1) / 2 ? batch : ((live + 1) / 2 > 0 ? (live + 1) / 2 : 1);
-            if (fly == 0 || __popcll(wait) >= want) break;
-            if (st == ST_FLY) {
-                const Shell s = sh[i];
-                const bool inward = (t < (R)0) && (b2 < s.r2_in);
-                const R arg = (inward ? s.r2_in : s.r2_out) - b2;
-                const R sq = P<R>::sqrt_(arg > (R)0 ? arg : (R)0);
-                const R tn = inward ? -sq : sq;
-                const R lb = tn - t > (R)0 ? tn - t : (R)0;
-                const R chiA = kA * s.rho, chiS = kS * s.rho;
-                const R dA = chiA * lb, dS = chiS * lb;
-                if (dA < tauA && dS < tauS) {
-                    // boundary crossing (Eq. 4); the central cavity is crossed in one jump
-                    tauA -= dA;
-                    tauS -= dS;
-                    const bool cav = inward && i == 0;
-                    t = cav ? -tn : tn;
-                    i += inward ? (cav ? 0 : -1) : 1;
-                    c_cross += cav ? 2u : 1u;
-                    if (i == n) {
-                        c_cross--;
-                        escape();
-                    }
-                } else if (events >= p.max_events) {
-                    term += p.eps[src] * (double)W;
-                    c_limit++;
-                    st = ST_DEAD;
-                } else {
-                    // the free path that runs out first ends the flight (Sect. 2.1)
-                    events++;
-                    const R lA = chiA > (R)0 ? tauA * P<R>::rcp(chiA) : P<R>::inf();
-                    const R lS = chiS > (R)0 ? tauS * P<R>::rcp(chiS) : P<R>::inf();
-                    const bool ab = lA <= lS;
-                    t += ab ? lA : lS;
-                    st = ab ? ST_ABS : ST_SCAT;
+        // ---- crossing sweep.  Both free paths fall by kappa rho l along a flight
+        // (Eq. 4), so the one that runs out first is fixed when they are drawn:
+        // the flight carries the smaller of tau_A / kappa_A and tau_S / kappa_S
+        // as a column of rho-weighted length and the type of its interaction.
+        // A lane that reaches its interaction parks; the wave stops stepping
+        // when enough lanes are parked.
+        {
+            const int live = __popcll(__ballot(st != ST_DONE));
+            const int half = (live + 1) / 2;
+            const int want = batch < half ? batch : (half > 0 ? half : 1);
+            for (;;) {
+                const unsigned long long fly = __ballot(st == ST_FLY);
+                if (fly == 0 || live - __popcll(fly) >= want) break;
+                if (st == ST_FLY) {
+                    const Shell s = P<R>::shell(ps);
+                    const bool inward = (t < (R)0) && (b2 < s.r2_in);
+                    const R arg = (inward ? s.r2_in : s.r2_out) - b2;
+                    const R sq = P<R>::sqrt_(arg > (R)0 ? arg : (R)0);
+                    const R tn = inward ? -sq : sq;
+                    const R ds = s.rho * (tn - t);
+                    const bool cross = ds < sig;
+                    const R t_evt = t + sig * s.inv_rho;
+                    sig -= ds;
+                    t = cross ? tn : t_evt;
+                    ps += cross ? (inward ? -1 : 1) : 0;
+                    lc.cross += cross ? 1u : 0u;
+                    st = cross ? ST_FLY : ST_EVT;
                 }
             }
         }
-        if (__ballot(st != ST_FLY && !done) == 0) break;  // nothing in flight, nothing pending
+        if (__ballot(st != ST_DONE && st != ST_FLY) == 0) break;  // nothing parked: all lanes finished
 
         // ---- event batch
-        // (package indices come from a wave-private pool refilled `chunk` at a time)
+        const int i = (int)(ps - sh);        // internal shell index
+        bool absorbing = false, scattering = false;
+        if (st == ST_EVT) {
+            if (ps == sentinel) {
+                // the flight left the cloud (the step into the sentinel is no crossing)
+                const double e = eps * (double)W;
+                if (src == 0) lc.esc0 += e; else lc.esc1 += e;
+                lc.escape++;
+                lc.cross--;
+                if (events == 0) lc.direct++;
+                st = ST_DEAD;
+            } else if (events >= o.max_events) {
+                lc.term += eps * (double)W;
+                lc.limit++;
+                st = ST_DEAD;
+            } else {
+                events++;
+                absorbing = ev_abs;
+                scattering = !ev_abs;
+            }
+        }
+
+        // refill lanes without a package from the wave-private pool, which takes
+        // `chunk` package indices from the global cursor at a time
         bool launching = false;
-        const unsigned long long need = __ballot(st == ST_DEAD && !done);
+        const unsigned long long need = __ballot(st == ST_DEAD);
         if (need) {
             const unsigned long long cnt = __popcll(need);
             const unsigned long long avail = pool_end - pool_next;
             unsigned long long fresh = 0;
             if (avail < cnt) {
                 const int leader = __ffsll((long long)need) - 1;
-                if (lane == leader) fresh = atomicAdd(&p.stats->cursor, p.chunk);
+                if (lane == leader) fresh = atomicAdd(cursor, chunk);
                 fresh = __shfl(fresh, leader, kWave);
             }
-            if (st == ST_DEAD && !done) {
+            if (st == ST_DEAD) {
                 const unsigned long long rank = __popcll(need & __lanemask_lt());
                 const unsigned long long gidx = rank < avail ? pool_next + rank : fresh + (rank - avail);
                 if (gidx >= total) {
-                    done = true;
+                    st = ST_DONE;
                 } else {
-                    src = gidx < p.n_ext ? 0 : 1;
-                    const unsigned long long pid = p.pid0[src] + (src ? gidx - p.n_ext : gidx);
+                    src = gidx < mc.n_ext ? 0 : 1;
+                    const unsigned long long pid = (src ? mc.pid0[1] + (gidx - mc.n_ext) : mc.pid0[0] + gidx);
+                    eps = src ? mc.eps[1] : mc.eps[0];
                     pid_lo = (uint32_t)pid;
                     pid_hi = (uint32_t)(pid >> 32);
                     blk = 0;
@@ -300,20 +344,18 @@ __device__ __forceinline__ void trace_body(const TraceParams &p, const typename 
             }
             if (avail < cnt) {
                 pool_next = fresh + (cnt - avail);
-                pool_end = fresh + p.chunk;
+                pool_end = fresh + chunk;
             } else {
                 pool_next += cnt;
             }
         }
-        const bool absorbing = st == ST_ABS;
-        const bool scattering = st == ST_SCAT;
         const bool ev = launching || absorbing || scattering;
 
         // absorption: deposit E into the shell; A_before locates this package's
         // slice [A_before, A_before + E] of the shell's absorbed power
-        const double E = absorbing ? p.eps[src] * (double)W : 0.0;
+        const double E = absorbing ? eps * (double)W : 0.0;
         double A_before = 0.0;
-        if (__ballot(absorbing)) A_before = fetch_add_energy<AGG>(p.A, i, E, absorbing);
+        if (__ballot(absorbing)) A_before = fetch_add_energy<AGG>(mc.A, i - cav, E, absorbing);
 
         Rand4 r1{0, 0, 0, 0}, r2b{0, 0, 0, 0};
         if (ev) r1 = philox(blk++, pid_lo, pid_hi, (uint32_t)src, key0, key1);
@@ -322,17 +364,16 @@ __device__ __forceinline__ void trace_body(const TraceParams &p, const typename 
         // new frequency: source spectrum at launch, difference spectrum at re-emission
         int row = 0;
         if (absorbing) {
-            const double astar = (A_before + (((double)r1.x + 0.5) * 0x1p-32) * E) * p.invM[i];
+            const double astar = (A_before + (((double)r1.x + 0.5) * 0x1p-32) * E) * mc.invM[i - cav];
             row = count_le(G, n_t, (R)astar);
-            if (row > n_t - 1) { row = n_t - 1; c_reabove++; }
-            c_abs++;
+            if (row > n_t - 1) { row = n_t - 1; lc.reabove++; }
+            lc.abs++;
         }
         if (launching || absorbing) {
             const R *tab = launching ? cdf + src * K : D + (size_t)row * K;
             k = min(count_le(tab, K, P<R>::uni(launching ? r1.x : r1.y)), K - 1);
-            const Dust d = dust[k];
-            kA = d.kA; kS = d.kS; gg = d.g; alb = d.alb;
         }
+        const Dust d = dust[k];
 
         // new direction: isotropic re-emission or Henyey-Greenstein scattering
         if (absorbing || scattering) {
@@ -341,16 +382,17 @@ __device__ __forceinline__ void trace_body(const TraceParams &p, const typename 
             R mun;
             if (absorbing) {
                 mun = (R)2 * P<R>::uni(r1.z) - (R)1;
-                if (p.reemit_uniform) {
-                    const Shell s = sh[i];
-                    const R rin = s.r_in;
+                if (o.reemit_uniform) {
+                    const Shell s = *ps;
+                    const R rin = P<R>::sqrt_(s.r2_in);
                     const R rout = P<R>::sqrt_(s.r2_out);
                     const R c3 = rin * rin * rin + P<R>::uni(r2b.y) * (rout * rout * rout - rin * rin * rin);
                     rr = P<R>::cbrt_(c3);
                     r2 = rr * rr;
                 }
             } else {
-                c_scat++;
+                lc.scat++;
+                const R gg = d.g;
                 const R mu = rr > (R)0 ? t * P<R>::rcp(rr) : (R)1;
                 const R u0 = P<R>::uni(r1.x);
                 R ct;
@@ -372,115 +414,157 @@ __device__ __forceinline__ void trace_body(const TraceParams &p, const typename 
         }
 
         // both free paths are redrawn after every event (Eq. 1)
-        if (ev) {
-            tauA = P<R>::nlog(P<R>::uni(absorbing ? r1.w : r1.z));
-            tauS = P<R>::nlog(P<R>::uni(absorbing ? r2b.x : r1.w));
-            st = ST_FLY;
-        }
+        R tauA = P<R>::nlog(P<R>::uni(absorbing ? r1.w : r1.z));
+        R tauS = P<R>::nlog(P<R>::uni(absorbing ? r2b.x : r1.w));
 
         // launch geometry and launch weights (Eqs. 2-3, Eq. 5, Eqs. 9-12)
         if (launching) {
-            c_launch++;
+            lc.launch++;
             if (src == 0) {
                 const R u1 = P<R>::uni(r1.y);
                 R mu;
-                if (p.k_bg == 0.5) {
+                if (o.k_bg == 0.5) {
                     mu = P<R>::sqrt_(u1);
                 } else {
-                    const R kb = (R)p.k_bg;
+                    const R kb = (R)o.k_bg;
                     mu = P<R>::powr(u1, kb);
                     W = (R)2 * kb * P<R>::powr(mu, (R)2 - (R)1 / kb);
                 }
-                i = n - 1;
+                ps = sentinel - 1;
                 t = -mu;
                 b2 = ((R)1 - mu) * ((R)1 + mu);
             } else {
-                i = 0;
+                ps = sh;            // the centre (inside the cavity shell when there is one)
                 b2 = 0;
-                t = sh[0].r_in;
-                if (p.cavity) c_cross++;
+                t = 0;
             }
-            if (p.ffi) {
+            if (o.ffi) {
                 // extinction optical depth along the whole first ray
-                const R kext = kA + kS;
                 R tau0 = 0, tt = t;
-                int ii = i;
-                for (;;) {
-                    const Shell s = sh[ii];
+                for (const Shell *q = ps; q != sentinel;) {
+                    const Shell s = *q;
                     const bool inward = (tt < (R)0) && (b2 < s.r2_in);
                     const R arg = (inward ? s.r2_in : s.r2_out) - b2;
                     const R sq = P<R>::sqrt_(arg > (R)0 ? arg : (R)0);
                     const R tn = inward ? -sq : sq;
                     const R lb = tn - tt > (R)0 ? tn - tt : (R)0;
-                    tau0 += kext * s.rho * lb;
+                    tau0 += d.kext * s.rho * lb;
                     tt = tn;
-                    if (inward) {
-                        if (ii == 0) tt = -tt; else ii--;
-                    } else if (++ii == n) {
-                        break;
-                    }
+                    q += inward ? -1 : 1;
                 }
                 if (!(tau0 > (R)0)) {
-                    escape();
+                    // no matter on the ray: the package leaves untouched
+                    if (src == 0) lc.esc0 += eps * (double)W; else lc.esc1 += eps * (double)W;
+                    lc.escape++;
+                    lc.direct++;
+                    launching = false;
+                    st = ST_DEAD;
                 } else {
                     const R pf = -P<R>::expm1_(-tau0);
-                    ffi_esc += p.eps[src] * (double)W * (double)(((R)1) - pf);
+                    lc.ffi += eps * (double)W * (double)(((R)1) - pf);
                     W *= pf;
                     const R tau = -P<R>::log1p_(-P<R>::uni(r1.z) * pf);
-                    if (P<R>::uni(r1.w) < alb) { tauS = tau * alb; tauA = P<R>::inf(); }
-                    else { tauA = tau * ((R)1 - alb); tauS = P<R>::inf(); }
+                    if (P<R>::uni(r1.w) < d.alb) { tauS = tau * d.alb; tauA = P<R>::inf(); }
+                    else { tauA = tau * ((R)1 - d.alb); tauS = P<R>::inf(); }
                 }
             }
             W0 = W;
         }
 
         // weight floor (Sect. 2.2.1)
-        if ((absorbing || scattering) && W < (R)p.w_floor * W0) {
-            term += p.eps[src] * (double)W;
-            c_floor++;
+        if ((absorbing || scattering) && W < (R)o.w_floor * W0) {
+            lc.term += eps * (double)W;
+            lc.floor++;
             st = ST_DEAD;
+        } else if (launching || absorbing || scattering) {
+            const R sA = tauA * d.inv_kA;
+            const R sS = tauS * d.inv_kS;
+            ev_abs = sA <= sS;
+            sig = ev_abs ? sA : sS;
+            st = ST_FLY;
         }
     }
 
-    // ---- flush per-lane counters: one atomic per wave and counter
-    const unsigned long long cs[9] = {c_launch, c_cross, c_scat, c_abs, c_escape,
-                                      c_direct, c_limit, c_floor, c_reabove};
+}
+
+// Sum the per-lane counters over the wave and add them to the launch statistics.
+__device__ __forceinline__ void flush_counters(const LaneCounters &lc, DevStats *stats) {
+    const int lane = __lane_id();
+    const unsigned long long cs[9] = {lc.launch, lc.cross, lc.scat, lc.abs, lc.escape,
+                                      lc.direct, lc.limit, lc.floor, lc.reabove};
     const int cidx[9] = {C_LAUNCH, C_CROSS, C_SCAT, C_ABS, C_ESCAPE, C_DIRECT, C_LIMIT, C_FLOOR, C_REEMIT_ABOVE};
 #pragma unroll
     for (int j = 0; j < 9; ++j) {
         const unsigned long long v = wave_sum_u64(cs[j]);
-        if (lane == 0 && v) atomicAdd(&p.stats->cnt[cidx[j]], v);
+        if (lane == 0 && v) atomicAdd(&stats->cnt[cidx[j]], v);
     }
-    const double ts[4] = {esc0, esc1, ffi_esc, term};
+    const double ts[4] = {lc.esc0, lc.esc1, lc.ffi, lc.term};
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const double v = wave_sum_f64(ts[j]);
-        if (lane == 0 && v != 0.0) unsafeAtomicAdd(&p.stats->tally[j], v);
+        if (lane == 0 && v != 0.0) unsafeAtomicAdd(&stats->tally[j], v);
     }
+}
+
+template <typename R>
+__device__ __forceinline__ void single_model(const TraceParams &p, const typename P<R>::Shell *sh,
+                                             ModelCtx<R> &mc, MethodOpts &o) {
+    mc.sh = sh;
+    mc.n = p.n;
+    mc.cav = p.cavity;
+    mc.invM = p.invM;
+    mc.A = p.A;
+    mc.eps[0] = p.eps[0];
+    mc.eps[1] = p.eps[1];
+    mc.n_ext = p.n_ext;
+    mc.n_ps = p.n_ps;
+    mc.pid0[0] = p.pid0[0];
+    mc.pid0[1] = p.pid0[1];
+    mc.seed = p.seed;
+    o.k_bg = p.k_bg;
+    o.ffi = p.ffi;
+    o.reemit_uniform = p.reemit_uniform;
+    o.batch = p.batch;
+    o.w_floor = p.w_floor;
+    o.max_events = p.max_events;
 }
 
 template <bool AGG>
 __global__ __launch_bounds__(kBlockFP32) void ire_trace_f32(TraceParams p) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int n = p.n, K = p.K, n_t = p.n_t;
+    const int nsh = p.n + p.cavity + 1, K = p.K, n_t = p.n_t;
     ShellF *s_sh = reinterpret_cast<ShellF *>(smem);
-    DustF *s_dust = reinterpret_cast<DustF *>(s_sh + n);
+    DustF *s_dust = reinterpret_cast<DustF *>(s_sh + nsh);
     float *s_cdf = reinterpret_cast<float *>(s_dust + K);
     float *s_G = s_cdf + 2 * K;
     float *s_D = s_G + n_t;
-    for (int j = threadIdx.x; j < n; j += blockDim.x) s_sh[j] = p.shf[j];
+    for (int j = threadIdx.x; j < nsh; j += blockDim.x) s_sh[j] = p.shf[j];
     for (int j = threadIdx.x; j < K; j += blockDim.x) s_dust[j] = p.dustf[j];
     for (int j = threadIdx.x; j < 2 * K; j += blockDim.x) s_cdf[j] = p.cdff[j];
     for (int j = threadIdx.x; j < n_t; j += blockDim.x) s_G[j] = p.Gf[j];
     const int nd = n_t * K;
     for (int j = threadIdx.x; j < nd; j += blockDim.x) s_D[j] = p.Df[j];
     __syncthreads();
-    trace_body<float, AGG>(p, s_sh, s_dust, s_cdf, s_G, s_D);
+    ModelCtx<float> mc;
+    MethodOpts o;
+    single_model<float>(p, s_sh, mc, o);
+    const long long gtid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    LaneCounters lc;
+    trace_model<float, AGG>(mc, o, s_dust, s_cdf, s_G, s_D, K, n_t, &p.stats->cursor, p.chunk,
+                            p.max_lanes > 0 && gtid >= p.max_lanes, lc);
+    flush_counters(lc, p.stats);
 }
 
 template <bool AGG>
 __global__ __launch_bounds__(256) void ire_trace_f64(TraceParams p) {
-    trace_body<double, AGG>(p, p.shd, p.dustd, p.cdfd, p.Gd, p.Dd);
+    ModelCtx<double> mc;
+    MethodOpts o;
+    single_model<double>(p, p.shd, mc, o);
+    const long long gtid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    LaneCounters lc;
+    trace_model<double, AGG>(mc, o, p.dustd, p.cdfd, p.Gd, p.Dd, p.K, p.n_t, &p.stats->cursor, p.chunk,
+                             p.max_lanes > 0 && gtid >= p.max_lanes, lc);
+    flush_counters(lc, p.stats);
 }
 
 __global__ void ire_zero(double *A, int n, DevStats *st, int clear_counts) {
@@ -523,10 +607,106 @@ __global__ void ire_finalize(FinalizeParams p) {
     p.T_out[i] = T;
 }
 
+// ---------------------------------------------------------------------------
+// Batched persistent launch: each workgroup takes work items (a range of one
+// model's packages) from a global cursor, stages that model's shells in LDS
+// next to the shared dust / G / re-emission tables, traces the range with all
+// its waves (package indices from an LDS cursor), and drains before the next.
+
+template <bool AGG>
+__global__ __launch_bounds__(kBlockFP32) void ire_trace_batch(BatchParams p) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ unsigned long long s_item;
+    __shared__ unsigned long long s_cursor;
+    const int K = p.K, n_t = p.n_t;
+    ShellF *s_sh = reinterpret_cast<ShellF *>(smem);
+    DustF *s_dust = reinterpret_cast<DustF *>(s_sh + p.max_table);
+    float *s_cdf = reinterpret_cast<float *>(s_dust + K);
+    float *s_G = s_cdf + 2 * K;
+    float *s_D = s_G + n_t;
+    for (int j = threadIdx.x; j < K; j += blockDim.x) s_dust[j] = p.dustf[j];
+    for (int j = threadIdx.x; j < 2 * K; j += blockDim.x) s_cdf[j] = p.cdff[j];
+    for (int j = threadIdx.x; j < n_t; j += blockDim.x) s_G[j] = p.Gf[j];
+    const int nd = n_t * K;
+    for (int j = threadIdx.x; j < nd; j += blockDim.x) s_D[j] = p.Df[j];
+
+    MethodOpts o;
+    o.k_bg = p.k_bg;
+    o.ffi = p.ffi;
+    o.reemit_uniform = p.reemit_uniform;
+    o.batch = p.batch;
+    o.w_floor = p.w_floor;
+    o.max_events = p.max_events;
+    LaneCounters lc;
+    for (;;) {
+        __syncthreads();  // every wave has finished the previous item: the shell slot is free
+        if (threadIdx.x == 0) {
+            s_item = atomicAdd(&p.stats->cursor, 1ull);
+            s_cursor = 0;
+        }
+        __syncthreads();
+        const unsigned long long it = s_item;
+        if (it >= (unsigned long long)p.n_items) break;
+        const BatchItemDev item = p.items[it];
+        const BatchModelDev bm = p.models[item.model];
+        const int nt = bm.n + bm.cav + 1;
+        for (int j = threadIdx.x; j < nt; j += blockDim.x) s_sh[j] = p.shells[bm.shell_off + j];
+        __syncthreads();
+        ModelCtx<float> mc;
+        mc.sh = s_sh;
+        mc.n = bm.n;
+        mc.cav = bm.cav;
+        mc.invM = p.invM + bm.acc_off;
+        mc.A = p.A + (size_t)bm.acc_off * kAccStride;
+        mc.eps[0] = bm.eps;
+        mc.eps[1] = bm.eps;
+        mc.n_ext = bm.src == 0 ? item.count : 0;
+        mc.n_ps = bm.src == 0 ? 0 : item.count;
+        mc.pid0[0] = item.first;
+        mc.pid0[1] = item.first;
+        mc.seed = bm.seed;
+        trace_model<float, AGG>(mc, o, s_dust, s_cdf, s_G, s_D, K, n_t, &s_cursor, 64ull, false, lc);
+    }
+    flush_counters(lc, p.stats);
+}
+
+__global__ void ire_zero_batch(double *A, size_t n_shells, DevStats *st) {
+    const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (size_t j = tid; j < n_shells; j += (size_t)gridDim.x * blockDim.x) A[j * kAccStride] = 0.0;
+    if (tid == 0) {
+        st->cursor = 0;
+        for (int j = 0; j < 16; ++j) st->cnt[j] = 0;
+        for (int j = 0; j < 8; ++j) st->tally[j] = 0.0;
+    }
+}
+
+// A -> T for every shell of every model (the models share the G(T) table)
+__global__ void ire_finalize_batch(BatchFinalizeParams p) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p.n_shells) return;
+    const double A = p.A[(size_t)i * kAccStride];
+    const double a = A * p.invM[i];
+    double T;
+    if (!(a >= p.Gd[0])) {
+        T = p.t_min;
+        atomicAdd(&p.stats->cnt[C_BELOW], 1ull);
+    } else if (a > p.Gd[p.n_t - 1]) {
+        T = p.t_max;
+        atomicAdd(&p.stats->cnt[C_ABOVE], 1ull);
+    } else {
+        int j = count_le(p.Gd, p.n_t, a) - 1;
+        j = j < 0 ? 0 : (j > p.n_t - 2 ? p.n_t - 2 : j);
+        const double f = (log(a) - p.lnG[j]) / (p.lnG[j + 1] - p.lnG[j]);
+        T = exp(p.lnT[j] + f * (p.lnT[j + 1] - p.lnT[j]));
+    }
+    p.A_out[i] = A;
+    p.T_out[i] = T;
+}
+
 }  // namespace
 
-size_t trace_lds_bytes(int n, int K, int n_t) {
-    return (size_t)n * sizeof(ShellF) + (size_t)K * sizeof(DustF) + (size_t)2 * K * sizeof(float) +
+size_t trace_lds_bytes(int n_table, int K, int n_t) {
+    return (size_t)n_table * sizeof(ShellF) + (size_t)K * sizeof(DustF) + (size_t)2 * K * sizeof(float) +
            (size_t)n_t * sizeof(float) + (size_t)n_t * K * sizeof(float);
 }
 
@@ -567,7 +747,32 @@ hipError_t launch_finalize(const FinalizeParams &p, hipStream_t s) {
     return hipGetLastError();
 }
 
-// The block size the FP32 tracer is compiled for.
+// The block size the FP32 tracers are compiled for.
 int trace_block_fp32() { return kBlockFP32; }
+
+hipError_t batch_configure(int aggregate, size_t lds) {
+    const void *f = aggregate ? reinterpret_cast<const void *>(&ire_trace_batch<true>)
+                              : reinterpret_cast<const void *>(&ire_trace_batch<false>);
+    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+hipError_t launch_trace_batch(const BatchParams &p, int aggregate, int grid, size_t lds, hipStream_t s) {
+    if (aggregate) hipLaunchKernelGGL(ire_trace_batch<true>, dim3(grid), dim3(kBlockFP32), lds, s, p);
+    else hipLaunchKernelGGL(ire_trace_batch<false>, dim3(grid), dim3(kBlockFP32), lds, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_batch(double *A, size_t n_shells, DevStats *st, hipStream_t s) {
+    size_t blocks = (n_shells + 255) / 256;
+    blocks = blocks < 1 ? 1 : (blocks > 4096 ? 4096 : blocks);
+    hipLaunchKernelGGL(ire_zero_batch, dim3((unsigned)blocks), dim3(256), 0, s, A, n_shells, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_batch(const BatchFinalizeParams &p, hipStream_t s) {
+    const int blocks = (p.n_shells + 255) / 256;
+    hipLaunchKernelGGL(ire_finalize_batch, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
 
 }  // namespace ire

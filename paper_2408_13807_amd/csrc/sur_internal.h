@@ -1,0 +1,78 @@
+// Internal layouts of the MLP surrogate (shared by sur_kernels.hip and sur_api.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sur {
+
+constexpr int kWidth = 256;    // hidden width
+constexpr int kFeatures = 6;   // cloud/shell parameters per row
+constexpr int kIn = 32;        // inputs padded to the MFMA k granularity
+
+// Parameter layout per ensemble member (FP32 master, flat):
+//   [0, kWidth*kIn)                 W_0 (row-major [out][in], inputs beyond kFeatures stay zero)
+//   (depth-1) blocks of kWidth^2    W_1 .. W_{depth-1}
+//   off_b:    depth*kWidth          hidden biases
+//   off_wout: kWidth                output weights
+//   off_bout: 1                     output bias
+// The BF16 weights W share the weight part of that layout; WT holds each block transposed.
+struct NetView {
+    int members, depth;
+    __bf16 *W, *WT;
+    float *b, *wout, *bout;
+    size_t w_stride, b_stride, p_stride;
+    size_t off_b, off_wout, off_bout;
+    float x_mean[kFeatures], x_inv_std[kFeatures];
+    float y_mean, y_std, y_inv_std;
+};
+
+struct TrainView {
+    int64_t batch;              // rows per member and step
+    float *xb, *yb;             // [M][batch][kFeatures], [M][batch] gathered mini-batch
+    __bf16 *x16;                // [M][batch][kIn] normalised inputs
+    __bf16 *h;                  // [M][depth][batch][kWidth] activations
+    float *ds;                  // [M][depth][batch][kWidth] SiLU'(z)
+    __bf16 *delta;              // [M][depth][batch][kWidth] d loss / d z
+    float *out, *g;             // [M][batch] outputs and d loss / d output
+    float *loss;                // [M] mean squared error of the step (normalised target)
+    float *grad, *master, *adam_m, *adam_v;  // [M][p_stride]
+};
+
+// Write one master parameter (member m, flat index q) into the BF16/FP32 copies the kernels read.
+__device__ __forceinline__ void scatter_param(const NetView &v, int m, size_t q, float p) {
+    if (q < v.off_b) {
+        v.W[(size_t)m * v.w_stride + q] = (__bf16)p;
+        size_t blk, K;
+        if (q < (size_t)kWidth * kIn) {
+            blk = 0;
+            K = kIn;
+        } else {
+            blk = (size_t)kWidth * kIn + ((q - (size_t)kWidth * kIn) / ((size_t)kWidth * kWidth)) * kWidth * kWidth;
+            K = kWidth;
+        }
+        const size_t e = q - blk;
+        const size_t o = e / K, i = e % K;
+        v.WT[(size_t)m * v.w_stride + blk + i * kWidth + o] = (__bf16)p;
+    } else if (q < v.off_wout) {
+        v.b[(size_t)m * v.b_stride + (q - v.off_b)] = p;
+    } else if (q < v.off_bout) {
+        v.wout[(size_t)m * kWidth + (q - v.off_wout)] = p;
+    } else {
+        v.bout[m] = p;
+    }
+}
+
+size_t predict_lds();
+hipError_t configure();
+hipError_t launch_predict(const NetView &v, const float *X, int64_t n, float *mean_logT, float *spread, hipStream_t s);
+// One training step on the batch in t (gathered from X, y when X is not null);
+// with `update`, an Adam step and the step counter increment follow.
+hipError_t launch_train_step(const NetView &v, const TrainView &t, const float *X, const float *y, int64_t n_data,
+                             unsigned long long seed, unsigned long long *step, float lr_max, float lr_min,
+                             unsigned long long total_steps, float beta1, float beta2, float eps, int update,
+                             hipStream_t s);
+hipError_t launch_sync_params(const NetView &v, const float *master, hipStream_t s);
+hipError_t launch_zero(float *a, size_t n, hipStream_t s);
+
+}  // namespace sur

@@ -1,0 +1,494 @@
+// MLP surrogate of the IRE temperature profile: BF16 MFMA kernels for gfx950.
+//
+// The network maps 6 cloud/shell parameters (padded to 32 inputs) through
+// `depth` hidden layers of width 256 with SiLU activations to log10 T.
+// Weights are BF16 (FP32 master copies for Adam), accumulation is FP32 in the
+// matrix cores (v_mfma_f32_32x32x16_bf16).  Every layer is computed as
+// D = W . H^T: the weights (row-major [out][in], read from L2) are the MFMA A
+// operand and the activations (row-major [row][feature], staged in LDS) the B
+// operand, so each lane's accumulators hold 4 consecutive output features of
+// one row and the epilogue stores 8 bytes at a time.
+//
+// MFMA 32x32x16 bf16 lane layout (wave64): A fragment of lane l = A[l&31][8(l>>5) .. +7],
+// B fragment = B[8(l>>5) .. +7][l&31] (given as B^T rows), accumulator r of lane l =
+// D[8(r>>2) + 4(l>>5) + (r&3)][l&31].
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sur_internal.h"
+
+namespace sur {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kW = kWidth;         // 256
+constexpr int kR = 128;            // rows per workgroup tile
+constexpr int kLd = kW + 8;        // LDS row stride (bf16) of activation tiles
+constexpr int kLdX = kIn + 8;      // LDS row stride of the input tile
+constexpr int kThreads = 256;      // 4 waves
+
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float dsilu(float z) {
+    const float s = 1.0f / (1.0f + __expf(-z));
+    return s * (1.0f + z * (1.0f - s));
+}
+
+__device__ __forceinline__ f32x16 mfma(const bf16x8 &a, const bf16x8 &b, const f32x16 &c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+// Normalised inputs of rows [row0, row0 + kR) into the LDS input tile (zero padded).
+__device__ __forceinline__ void load_inputs(const float *X, int64_t n, int64_t row0, const NetView &v, __bf16 *xs) {
+    for (int j = threadIdx.x; j < kR * kIn; j += blockDim.x) {
+        const int r = j / kIn, c = j % kIn;
+        const int64_t row = row0 + r;
+        float x = 0.0f;
+        if (c < kFeatures && row < n) x = (X[row * kFeatures + c] - v.x_mean[c]) * v.x_inv_std[c];
+        xs[r * kLdX + c] = (__bf16)x;
+    }
+}
+
+// One hidden layer for the kR rows in LDS: hout = SiLU(W hin + b).  Wave w
+// computes output features [64w, 64w + 64) for all rows.  With TRAIN the
+// activation and SiLU'(z) are also stored to global memory (rows < n).
+template <bool TRAIN>
+__device__ __forceinline__ void layer_fwd(const __bf16 *W, const float *bias, int K, const __bf16 *hin, int ldin, __bf16 *hout,
+                          __bf16 *h_g, float *ds_g, int64_t row0, int64_t n) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int half = lane >> 5, l32 = lane & 31;
+    f32x16 acc[2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = f32x16{};
+    for (int kk = 0; kk < K; kk += 16) {
+        bf16x8 wa[2], hb[4];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int o = wave * 64 + a * 32 + l32;
+            wa[a] = *reinterpret_cast<const bf16x8 *>(W + (size_t)o * K + kk + 8 * half);
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) hb[b] = *reinterpret_cast<const bf16x8 *>(hin + (b * 32 + l32) * ldin + kk + 8 * half);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = mfma(wa[a], hb[b], acc[a][b]);
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int row = b * 32 + l32;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int o = wave * 64 + a * 32 + 8 * g + 4 * half;
+                bf16x4 hv;
+                float dv[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float z = acc[a][b][4 * g + q] + bias[o + q];
+                    hv[q] = (__bf16)silu(z);
+                    dv[q] = dsilu(z);
+                }
+                *reinterpret_cast<bf16x4 *>(hout + row * kLd + o) = hv;
+                if (TRAIN && row0 + row < n) {
+                    *reinterpret_cast<bf16x4 *>(h_g + (row0 + row) * kW + o) = hv;
+                    *reinterpret_cast<float4 *>(ds_g + (row0 + row) * kW + o) = float4{dv[0], dv[1], dv[2], dv[3]};
+                }
+            }
+        }
+}
+
+// Output layer: y = w_out . h + b_out for the kR rows (two threads per row).
+__device__ __forceinline__ float out_row(const __bf16 *h, const float *wout, float bout) {
+    const int r = threadIdx.x >> 1, part = threadIdx.x & 1;
+    float s = 0.0f;
+    for (int c = part * 128; c < part * 128 + 128; ++c) s += (float)h[r * kLd + c] * wout[c];
+    s += __shfl_xor(s, 1, 64);
+    return s + bout;
+}
+
+// ---------------------------------------------------------------------------
+// Inference: every member on every row; mean log10 T and relative spread of T.
+
+__global__ __launch_bounds__(kThreads) void sur_predict_kernel(NetView v, const float *X, int64_t n, float *mean_logT,
+                                                               float *spread) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __bf16 *xs = reinterpret_cast<__bf16 *>(smem);
+    __bf16 *h0 = xs + kR * kLdX;
+    __bf16 *h1 = h0 + kR * kLd;
+    const int64_t row0 = (int64_t)blockIdx.x * kR;
+    load_inputs(X, n, row0, v, xs);
+    float s_log = 0.0f, s_T = 0.0f, s_T2 = 0.0f;
+    for (int m = 0; m < v.members; ++m) {
+        const __bf16 *W = v.W + (size_t)m * v.w_stride;
+        const float *b = v.b + (size_t)m * v.b_stride;
+        __syncthreads();
+        layer_fwd<false>(W, b, kIn, xs, kLdX, h0, nullptr, nullptr, row0, n);
+        __bf16 *hin = h0, *hout = h1;
+        for (int l = 1; l < v.depth; ++l) {
+            __syncthreads();
+            layer_fwd<false>(W + (size_t)kW * kIn + (size_t)(l - 1) * kW * kW, b + l * kW, kW, hin, kLd, hout,
+                             nullptr, nullptr, row0, n);
+            __bf16 *t = hin; hin = hout; hout = t;
+        }
+        __syncthreads();
+        const float y = out_row(hin, v.wout + (size_t)m * kW, v.bout[m]);
+        const float lt = y * v.y_std + v.y_mean;       // log10 T of this member
+        const float T = exp10f(lt);
+        s_log += lt;
+        s_T += T;
+        s_T2 += T * T;
+    }
+    if ((threadIdx.x & 1) == 0) {
+        const int64_t row = row0 + (threadIdx.x >> 1);
+        if (row < n) {
+            const float M = (float)v.members;
+            const float mT = s_T / M;
+            const float var = fmaxf(s_T2 / M - mT * mT, 0.0f) * (v.members > 1 ? M / (M - 1.0f) : 0.0f);
+            mean_logT[row] = s_log / M;
+            spread[row] = sqrtf(var) / mT;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Training, one launch per stage; blockIdx.y selects the ensemble member.
+
+// Forward of a batch: stores every hidden activation and SiLU'(z), the output,
+// and the output-layer gradient g = d loss / d y of the mean squared error.
+__global__ __launch_bounds__(kThreads) void sur_train_fwd(NetView v, TrainView t) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __bf16 *xs = reinterpret_cast<__bf16 *>(smem);
+    __bf16 *h0 = xs + kR * kLdX;
+    __bf16 *h1 = h0 + kR * kLd;
+    const int m = blockIdx.y;
+    const int64_t n = t.batch;
+    const int64_t row0 = (int64_t)blockIdx.x * kR;
+    const __bf16 *W = v.W + (size_t)m * v.w_stride;
+    const float *b = v.b + (size_t)m * v.b_stride;
+    const float *X = t.xb + (size_t)m * n * kFeatures;
+    load_inputs(X, n, row0, v, xs);
+    // keep the normalised input tile for the first layer's weight gradient
+    for (int j = threadIdx.x; j < kR * kIn; j += blockDim.x) {
+        const int r = j / kIn, c = j % kIn;
+        if (row0 + r < n) t.x16[(size_t)m * n * kIn + (row0 + r) * kIn + c] = xs[r * kLdX + c];
+    }
+    __syncthreads();
+    const size_t act = (size_t)m * v.depth * n * kW;  // per member: depth x [n][256]
+    layer_fwd<true>(W, b, kIn, xs, kLdX, h0, t.h + act, t.ds + act, row0, n);
+    __bf16 *hin = h0, *hout = h1;
+    for (int l = 1; l < v.depth; ++l) {
+        __syncthreads();
+        layer_fwd<true>(W + (size_t)kW * kIn + (size_t)(l - 1) * kW * kW, b + l * kW, kW, hin, kLd, hout,
+                        t.h + act + (size_t)l * n * kW, t.ds + act + (size_t)l * n * kW, row0, n);
+        __bf16 *tmp = hin; hin = hout; hout = tmp;
+    }
+    __syncthreads();
+    const float y = out_row(hin, v.wout + (size_t)m * kW, v.bout[m]);
+    if ((threadIdx.x & 1) == 0) {
+        const int64_t row = row0 + (threadIdx.x >> 1);
+        if (row < n) {
+            const float target = (t.yb[(size_t)m * n + row] - v.y_mean) * v.y_inv_std;
+            const float d = y - target;
+            t.out[(size_t)m * n + row] = y;
+            t.g[(size_t)m * n + row] = 2.0f * d / (float)n;
+            atomicAdd(&t.loss[m], d * d / (float)n);
+        }
+    }
+}
+
+// Backward through the hidden layers: delta_top = g w_out (.) SiLU'(z_top), then
+// delta_{l-1} = (W_l^T delta_l) (.) SiLU'(z_{l-1}); every delta is stored (BF16).
+__global__ __launch_bounds__(kThreads) void sur_train_bwd(NetView v, TrainView t) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __bf16 *d0 = reinterpret_cast<__bf16 *>(smem);
+    __bf16 *d1 = d0 + kR * kLd;
+    const int m = blockIdx.y;
+    const int64_t n = t.batch;
+    const int64_t row0 = (int64_t)blockIdx.x * kR;
+    const int L = v.depth;
+    const size_t act = (size_t)m * L * n * kW;
+    const float *wout = v.wout + (size_t)m * kW;
+    // top delta
+    {
+        const float *ds = t.ds + act + (size_t)(L - 1) * n * kW;
+        __bf16 *dg = t.delta + act + (size_t)(L - 1) * n * kW;
+        for (int j = threadIdx.x; j < kR * kW; j += blockDim.x) {
+            const int r = j / kW, c = j % kW;
+            const int64_t row = row0 + r;
+            float d = 0.0f;
+            if (row < n) d = t.g[(size_t)m * n + row] * wout[c] * ds[row * kW + c];
+            const __bf16 db = (__bf16)d;
+            d0[r * kLd + c] = db;
+            if (row < n) dg[row * kW + c] = db;
+        }
+    }
+    const __bf16 *WT = v.WT + (size_t)m * v.w_stride;
+    __bf16 *din = d0, *dout = d1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int half = lane >> 5, l32 = lane & 31;
+    for (int l = L - 1; l >= 1; --l) {
+        __syncthreads();
+        // delta_{l-1}[row][k] = sum_o W_l[o][k] delta_l[row][o]: A = W_l^T ([in][out]), B = delta_l
+        const __bf16 *A = WT + (size_t)kW * kIn + (size_t)(l - 1) * kW * kW;
+        f32x16 acc[2][4];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int bb = 0; bb < 4; ++bb) acc[a][bb] = f32x16{};
+        for (int kk = 0; kk < kW; kk += 16) {
+            bf16x8 wa[2], hb[4];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+                wa[a] = *reinterpret_cast<const bf16x8 *>(A + (size_t)(wave * 64 + a * 32 + l32) * kW + kk + 8 * half);
+#pragma unroll
+            for (int bb = 0; bb < 4; ++bb)
+                hb[bb] = *reinterpret_cast<const bf16x8 *>(din + (bb * 32 + l32) * kLd + kk + 8 * half);
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int bb = 0; bb < 4; ++bb) acc[a][bb] = mfma(wa[a], hb[bb], acc[a][bb]);
+        }
+        const float *ds = t.ds + act + (size_t)(l - 1) * n * kW;
+        __bf16 *dg = t.delta + act + (size_t)(l - 1) * n * kW;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int bb = 0; bb < 4; ++bb) {
+                const int r = bb * 32 + l32;
+                const int64_t row = row0 + r;
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const int k = wave * 64 + a * 32 + 8 * g + 4 * half;
+                    float4 dsv = row < n ? *reinterpret_cast<const float4 *>(ds + row * kW + k) : float4{0, 0, 0, 0};
+                    bf16x4 dv;
+                    dv[0] = (__bf16)(acc[a][bb][4 * g + 0] * dsv.x);
+                    dv[1] = (__bf16)(acc[a][bb][4 * g + 1] * dsv.y);
+                    dv[2] = (__bf16)(acc[a][bb][4 * g + 2] * dsv.z);
+                    dv[3] = (__bf16)(acc[a][bb][4 * g + 3] * dsv.w);
+                    *reinterpret_cast<bf16x4 *>(dout + r * kLd + k) = dv;
+                    if (row < n) *reinterpret_cast<bf16x4 *>(dg + row * kW + k) = dv;
+                }
+            }
+        __bf16 *tmp = din; din = dout; dout = tmp;
+    }
+}
+
+// Weight gradients, split over groups of kWgChunks row tiles: dW_l[o][i] += sum_rows
+// delta_l[row][o] x_{l-1}[row][i], with x_0 the (padded) input and x_l the activation of
+// layer l; db_l[o] += sum_rows delta_l[row][o].  blockIdx.x = row group, blockIdx.y =
+// member * depth + layer.  Tiles are transposed into LDS so both MFMA operands read 8
+// consecutive rows; each workgroup adds its partial sums with one atomic per element.
+constexpr int kWgChunks = 8;
+
+__global__ __launch_bounds__(kThreads) void sur_train_wgrad(NetView v, TrainView t) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int m = blockIdx.y / v.depth, l = blockIdx.y % v.depth;
+    const int64_t n = t.batch;
+    const int Kin = l == 0 ? kIn : kW;
+    constexpr int kLt = kR + 8;                        // LDS stride of transposed tiles
+    __bf16 *dT = reinterpret_cast<__bf16 *>(smem);     // [256][kR]
+    __bf16 *xT = dT + kW * kLt;                        // [128][kR] (one block of inputs)
+    const size_t act = (size_t)m * v.depth * n * kW;
+    const __bf16 *dg = t.delta + act + (size_t)l * n * kW;
+    const __bf16 *xg = l == 0 ? t.x16 + (size_t)m * n * kIn : t.h + act + (size_t)(l - 1) * n * kW;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int half = lane >> 5, l32 = lane & 31;
+    float *gW = t.grad + (size_t)m * v.p_stride + (l == 0 ? 0 : (size_t)kW * kIn + (size_t)(l - 1) * kW * kW);
+    float *gb = t.grad + (size_t)m * v.p_stride + v.off_b + (size_t)l * kW;
+    float bsum = 0.0f;                                 // bias partial of feature threadIdx.x
+    for (int ib = 0; ib < Kin; ib += 128) {
+        const int width = Kin - ib < 128 ? Kin - ib : 128;
+        const int nb = width / 32;
+        f32x16 acc[2][4];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int bb = 0; bb < 4; ++bb) acc[a][bb] = f32x16{};
+        for (int ch = 0; ch < kWgChunks; ++ch) {
+            const int64_t row0 = ((int64_t)blockIdx.x * kWgChunks + ch) * kR;
+            if (row0 >= n) break;
+            __syncthreads();
+            for (int j = threadIdx.x; j < kR * kW; j += blockDim.x) {
+                const int r = j / kW, c = j % kW;
+                dT[c * kLt + r] = row0 + r < n ? dg[(row0 + r) * kW + c] : (__bf16)0.0f;
+            }
+            for (int j = threadIdx.x; j < kR * width; j += blockDim.x) {
+                const int r = j / width, c = j % width;
+                xT[c * kLt + r] = row0 + r < n ? xg[(row0 + r) * Kin + ib + c] : (__bf16)0.0f;
+            }
+            __syncthreads();
+            if (ib == 0)
+                for (int r = 0; r < kR; ++r) bsum += (float)dT[threadIdx.x * kLt + r];
+            for (int kk = 0; kk < kR; kk += 16) {
+                bf16x8 da[2], xb[4];
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+                    da[a] = *reinterpret_cast<const bf16x8 *>(dT + (wave * 64 + a * 32 + l32) * kLt + kk + 8 * half);
+#pragma unroll
+                for (int bb = 0; bb < 4; ++bb)
+                    if (bb < nb) xb[bb] = *reinterpret_cast<const bf16x8 *>(xT + (bb * 32 + l32) * kLt + kk + 8 * half);
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int bb = 0; bb < 4; ++bb)
+                        if (bb < nb) acc[a][bb] = mfma(da[a], xb[bb], acc[a][bb]);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int bb = 0; bb < 4; ++bb) {
+                if (bb >= nb) continue;
+                const int i = ib + bb * 32 + l32;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int o = wave * 64 + a * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                    atomicAdd(&gW[(size_t)o * Kin + i], acc[a][bb][r]);
+                }
+            }
+    }
+    atomicAdd(&gb[threadIdx.x], bsum);
+}
+
+// Output-layer gradients: dw_out[c] = sum_rows g h_top[c], db_out = sum_rows g.
+__global__ void sur_train_outgrad(NetView v, TrainView t) {
+    const int m = blockIdx.y;
+    const int64_t n = t.batch;
+    const int c = threadIdx.x;
+    const size_t act = (size_t)m * v.depth * n * kW + (size_t)(v.depth - 1) * n * kW;
+    const int64_t r0 = (int64_t)blockIdx.x * 256, r1 = r0 + 256 < n ? r0 + 256 : n;
+    float s = 0.0f, sg = 0.0f;
+    for (int64_t r = r0; r < r1; ++r) {
+        const float g = t.g[(size_t)m * n + r];
+        s += g * (float)t.h[act + r * kW + c];
+        sg += g;
+    }
+    float *gp = t.grad + (size_t)m * v.p_stride;
+    atomicAdd(&gp[v.off_wout + c], s);
+    if (c == 0) atomicAdd(&gp[v.off_bout], sg);
+}
+
+// Adam on the FP32 master parameters with a cosine learning-rate schedule over
+// total_steps; refreshes the BF16 weights and their transposes and clears the gradients.
+__global__ void sur_adam(NetView v, TrainView t, const unsigned long long *step, float lr_max, float lr_min,
+                         unsigned long long total_steps, float beta1, float beta2, float eps) {
+    const unsigned long long s = *step;
+    const float frac = total_steps > 0 ? fminf((float)s / (float)total_steps, 1.0f) : 0.0f;
+    const float lr = lr_min + 0.5f * (lr_max - lr_min) * (1.0f + cospif(frac));
+    const float bc1 = 1.0f - powf(beta1, (float)(s + 1));
+    const float bc2 = 1.0f - powf(beta2, (float)(s + 1));
+    const size_t total = (size_t)v.members * v.p_stride;
+    for (size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x; j < total; j += (size_t)gridDim.x * blockDim.x) {
+        const float g = t.grad[j];
+        const float mo = beta1 * t.adam_m[j] + (1.0f - beta1) * g;
+        const float ve = beta2 * t.adam_v[j] + (1.0f - beta2) * g * g;
+        t.adam_m[j] = mo;
+        t.adam_v[j] = ve;
+        const float p = t.master[j] - lr * (mo / bc1) / (sqrtf(ve / bc2) + eps);
+        t.master[j] = p;
+        t.grad[j] = 0.0f;
+        scatter_param(v, (int)(j / v.p_stride), j % v.p_stride, p);
+    }
+}
+
+// Copy master parameters (all members) into the BF16 weights and FP32 biases.
+__global__ void sur_sync_params(NetView v, const float *master) {
+    const size_t total = (size_t)v.members * v.p_stride;
+    for (size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x; j < total; j += (size_t)gridDim.x * blockDim.x)
+        scatter_param(v, (int)(j / v.p_stride), j % v.p_stride, master[j]);
+}
+
+// Gather a random mini-batch per member (rows drawn with replacement by hashing\n// seed, step and slot with splitmix64).
+__global__ void sur_gather(const float *X, const float *y, int64_t n_data, TrainView t, const unsigned long long *step,
+                           unsigned long long seed, int members) {
+    const int64_t B = t.batch;
+    const unsigned long long s = *step;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < B * members;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        // splitmix64 of (seed, step, slot) picks the row
+        unsigned long long z = seed + 0x9E3779B97F4A7C15ull * (s * (unsigned long long)(B * members) + (unsigned long long)j + 1);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        const int64_t row = (int64_t)(z % (unsigned long long)n_data);
+        for (int c = 0; c < kFeatures; ++c) t.xb[j * kFeatures + c] = X[row * kFeatures + c];
+        t.yb[j] = y[row];
+    }
+}
+
+__global__ void sur_zero(float *a, size_t n) {
+    for (size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (size_t)gridDim.x * blockDim.x) a[j] = 0.0f;
+}
+
+__global__ void sur_step_inc(unsigned long long *step) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *step += 1;
+}
+
+}  // namespace
+
+size_t predict_lds() { return (size_t)kR * kLdX * 2 + (size_t)2 * kR * kLd * 2; }
+size_t bwd_lds() { return (size_t)2 * kR * kLd * 2; }
+size_t wgrad_lds() { return (size_t)(kW + 128) * (kR + 8) * 2; }
+
+hipError_t configure() {
+    hipError_t e;
+    if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(&sur_predict_kernel),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)predict_lds())) != hipSuccess)
+        return e;
+    if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(&sur_train_fwd),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)predict_lds())) != hipSuccess)
+        return e;
+    if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(&sur_train_bwd),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)bwd_lds())) != hipSuccess)
+        return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&sur_train_wgrad),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)wgrad_lds());
+}
+
+hipError_t launch_predict(const NetView &v, const float *X, int64_t n, float *mean_logT, float *spread, hipStream_t s) {
+    const int64_t blocks = (n + kR - 1) / kR;
+    hipLaunchKernelGGL(sur_predict_kernel, dim3((unsigned)blocks), dim3(kThreads), predict_lds(), s, v, X, n,
+                       mean_logT, spread);
+    return hipGetLastError();
+}
+
+hipError_t launch_train_step(const NetView &v, const TrainView &t, const float *X, const float *y, int64_t n_data,
+                             unsigned long long seed, unsigned long long *step, float lr_max, float lr_min,
+                             unsigned long long total_steps, float beta1, float beta2, float eps, int update,
+                             hipStream_t s) {
+    const int M = v.members;
+    const bool gather = X != nullptr;
+    const unsigned blocks = (unsigned)((t.batch + kR - 1) / kR);
+    const unsigned groups = (unsigned)((t.batch + (int64_t)kR * kWgChunks - 1) / ((int64_t)kR * kWgChunks));
+    if (gather) hipLaunchKernelGGL(sur_gather, dim3(256), dim3(256), 0, s, X, y, n_data, t, step, seed, M);
+    hipLaunchKernelGGL(sur_zero, dim3(1), dim3(64), 0, s, t.loss, (size_t)M);
+    hipLaunchKernelGGL(sur_train_fwd, dim3(blocks, M), dim3(kThreads), predict_lds(), s, v, t);
+    hipLaunchKernelGGL(sur_train_bwd, dim3(blocks, M), dim3(kThreads), bwd_lds(), s, v, t);
+    hipLaunchKernelGGL(sur_train_wgrad, dim3(groups, M * v.depth), dim3(kThreads), wgrad_lds(), s, v, t);
+    hipLaunchKernelGGL(sur_train_outgrad, dim3((unsigned)((t.batch + 255) / 256), M), dim3(kW), 0, s, v, t);
+    if (update) {
+        hipLaunchKernelGGL(sur_adam, dim3(512), dim3(256), 0, s, v, t, step, lr_max, lr_min, total_steps, beta1,
+                           beta2, eps);
+        hipLaunchKernelGGL(sur_step_inc, dim3(1), dim3(64), 0, s, step);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sync_params(const NetView &v, const float *master, hipStream_t s) {
+    hipLaunchKernelGGL(sur_sync_params, dim3(512), dim3(256), 0, s, v, master);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(float *a, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(sur_zero, dim3(512), dim3(256), 0, s, a, n);
+    return hipGetLastError();
+}
+
+
+}  // namespace sur

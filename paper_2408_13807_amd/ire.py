@@ -26,7 +26,13 @@ IRE_FP64 = 1
 EXPORTS = ("ire_default_options", "ire_create", "ire_destroy", "ire_set_shells", "ire_set_dust",
            "ire_set_temperature_grid", "ire_set_external_field", "ire_set_point_source",
            "ire_set_options", "ire_run", "ire_begin", "ire_advance", "ire_reset", "ire_sync",
-           "ire_get_results", "ire_get_stats", "ire_get_results_dev", "ire_last_error", "ire_planck")
+           "ire_get_results", "ire_get_stats", "ire_get_results_dev", "ire_last_error", "ire_planck",
+           "ire_batch_default_options", "ire_batch_create", "ire_batch_destroy", "ire_batch_set_dust",
+           "ire_batch_set_temperature_grid", "ire_batch_set_sources", "ire_batch_set_models",
+           "ire_batch_set_options", "ire_batch_run", "ire_batch_get", "ire_batch_autotune",
+           "ire_batch_last_error")
+IRE_SRC_EXTERNAL = 0
+IRE_SRC_POINT = 1
 
 
 class Options(ct.Structure):
@@ -41,6 +47,25 @@ class Stats(ct.Structure):
         (f, ct.c_uint64) for f in ("n_launch", "n_cross", "n_scat", "n_abs", "n_escape", "n_direct",
                                    "n_limit", "n_floor", "n_below", "n_above", "n_reemit_above")] + [
         ("ms_tables", ct.c_float), ("ms_trace", ct.c_float), ("ms_finalize", ct.c_float)]
+
+
+class ModelDesc(ct.Structure):
+    _fields_ = [("n_shells", ct.c_int32), ("source", ct.c_int32), ("scale", ct.c_double),
+                ("n_packages", ct.c_uint64), ("seed", ct.c_uint64)]
+
+
+class BatchOptions(ct.Structure):
+    _fields_ = [("k_bg", ct.c_double), ("ffi", ct.c_int32), ("w_floor", ct.c_double),
+                ("max_events", ct.c_uint64), ("reemit_uniform", ct.c_int32), ("aggregate", ct.c_int32),
+                ("batch", ct.c_int32), ("item_packages", ct.c_uint64), ("use_graph", ct.c_int32)]
+
+
+class BatchStats(ct.Structure):
+    _fields_ = [("L_total", ct.c_double), ("escaped", ct.c_double), ("ffi_escaped", ct.c_double),
+                ("terminated", ct.c_double)] + [
+        (f, ct.c_uint64) for f in ("n_launch", "n_cross", "n_scat", "n_abs", "n_escape", "n_limit", "n_floor",
+                                   "n_below", "n_above", "n_models", "n_items", "n_shells")] + [
+        ("ms_run", ct.c_float)]
 
 
 class IREError(RuntimeError):
@@ -85,6 +110,20 @@ _lib.ire_get_results_dev.argtypes = [_H, ct.c_void_p, ct.c_void_p, ct.c_void_p]
 _lib.ire_last_error.argtypes = [_H]
 _lib.ire_last_error.restype = ct.c_char_p
 _lib.ire_planck.argtypes = [ct.c_int32, _DP, ct.c_double, _DP]
+_lib.ire_batch_default_options.argtypes = [ct.POINTER(BatchOptions)]
+_lib.ire_batch_create.argtypes = [ct.c_int, ct.POINTER(_H)]
+_lib.ire_batch_destroy.argtypes = [_H]
+_lib.ire_batch_destroy.restype = None
+_lib.ire_batch_set_dust.argtypes = [_H, ct.c_int32, _DP, _DP, _DP, _DP]
+_lib.ire_batch_set_temperature_grid.argtypes = [_H, ct.c_double, ct.c_double, ct.c_int32]
+_lib.ire_batch_set_sources.argtypes = [_H, _DP, _DP]
+_lib.ire_batch_set_models.argtypes = [_H, ct.c_int32, ct.POINTER(ModelDesc), _DP, _DP]
+_lib.ire_batch_set_options.argtypes = [_H, ct.POINTER(BatchOptions)]
+_lib.ire_batch_run.argtypes = [_H, ct.c_void_p]
+_lib.ire_batch_get.argtypes = [_H, _DP, _DP, ct.POINTER(BatchStats)]
+_lib.ire_batch_autotune.argtypes = [_H, ct.c_double, ct.c_char_p, ct.POINTER(BatchOptions)]
+_lib.ire_batch_last_error.argtypes = [_H]
+_lib.ire_batch_last_error.restype = ct.c_char_p
 
 
 def library() -> ct.CDLL:
@@ -232,3 +271,113 @@ def run_model(model: dict, n_ext: int = 0, n_ps: int = 0, seed: int = 1, device:
         m.set_options(**opts)
         m.run(n_ext, n_ps, seed, stream)
         return m.results(allow_limit=allow_limit)
+
+
+def default_batch_options(**kw) -> BatchOptions:
+    o = BatchOptions()
+    _lib.ire_batch_default_options(ct.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+class IREBatch:
+    """Many cloud models sharing dust, temperature grid and source shapes, run
+    in one persistent launch (ire_batch_* of include/ire.h)."""
+
+    def __init__(self, device: int = 0):
+        h = _H()
+        rc = _lib.ire_batch_create(int(device), ct.byref(h))
+        if rc:
+            raise IREError(rc, f"ire_batch_create(device={device}) failed")
+        self._h = h
+        self.n_shells = 0
+        self.offsets = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.ire_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, rc: int, allow_limit: bool = False):
+        if rc == IRE_OK or (allow_limit and rc == IRE_E_LIMIT):
+            return rc
+        raise IREError(rc, _lib.ire_batch_last_error(self._h).decode())
+
+    def set_dust(self, nu, kabs, albedo, g):
+        a = [_arr(x) for x in (nu, kabs, albedo, g)]
+        self._check(_lib.ire_batch_set_dust(self._h, len(a[0][0]), *[p for _, p in a]))
+
+    def set_temperature_grid(self, t_min: float, t_max: float, n_t: int):
+        self._check(_lib.ire_batch_set_temperature_grid(self._h, float(t_min), float(t_max), int(n_t)))
+
+    def set_sources(self, J_shape=None, S_shape=None):
+        j, pj = _arr(J_shape)
+        s, ps = _arr(S_shape)
+        self._check(_lib.ire_batch_set_sources(self._h, pj, ps))
+
+    def set_models(self, n_shells, source, scale, n_packages, seeds, r_edges_flat, rho_flat):
+        M = len(n_shells)
+        descs = (ModelDesc * M)()
+        for m in range(M):
+            descs[m] = ModelDesc(int(n_shells[m]), int(source[m]), float(scale[m]), int(n_packages[m]),
+                                 int(seeds[m]))
+        r, pr = _arr(r_edges_flat)
+        d, pd = _arr(rho_flat)
+        self._check(_lib.ire_batch_set_models(self._h, M, descs, pr, pd))
+        self.n_shells = int(np.sum(n_shells))
+        self.offsets = np.concatenate([[0], np.cumsum(n_shells)]).astype(np.int64)
+
+    def set_options(self, **kw):
+        self._check(_lib.ire_batch_set_options(self._h, ct.byref(default_batch_options(**kw))))
+
+    def run(self, stream=None):
+        self._check(_lib.ire_batch_run(self._h, _stream_ptr(stream)))
+
+    def results(self, allow_limit: bool = False) -> dict:
+        A = np.zeros(self.n_shells)
+        T = np.zeros(self.n_shells)
+        st = BatchStats()
+        rc = self._check(_lib.ire_batch_get(self._h, A.ctypes.data_as(_DP), T.ctypes.data_as(_DP), ct.byref(st)),
+                         allow_limit)
+        return dict(A=A, T=T, stats={f: getattr(st, f) for f, _ in BatchStats._fields_}, rc=rc)
+
+    def autotune(self, fraction: float = 0.02, cache_path: str | None = None) -> dict:
+        o = BatchOptions()
+        self._check(_lib.ire_batch_autotune(self._h, float(fraction),
+                                            cache_path.encode() if cache_path else None, ct.byref(o)))
+        return {f: getattr(o, f) for f, _ in BatchOptions._fields_}
+
+
+def batch_from_workloads(params: dict, models: list[int] | None = None, device: int = 0,
+                         package_scale: float = 1.0) -> IREBatch:
+    """An IREBatch holding models of a batched parameter study (see workloads.batch_parameters)."""
+    from paper_2408_13807_amd import workloads as wl
+    idx = list(range(len(params["n"]))) if models is None else list(models)
+    b = IREBatch(device)
+    d = wl.synthetic_dust()
+    b.set_dust(d["nu"], d["kabs"], d["albedo"], d["g"])
+    b.set_temperature_grid(3.0, 1600.0, 512)
+    b.set_sources(wl.isrf(d["nu"]), wl.blackbody(d["nu"], 5000.0))
+    r_all, rho_all, n_sh, src, scale, npk, seeds = [], [], [], [], [], [], []
+    for m in idx:
+        mm = wl.batch_model(params, m)
+        r_all.append(mm["r_edges"])
+        rho_all.append(mm["rho"])
+        n_sh.append(len(mm["rho"]))
+        central = int(params["central"][m])
+        src.append(IRE_SRC_POINT if central else IRE_SRC_EXTERNAL)
+        scale.append(float(params["L"][m]) if central else float(params["field_scale"][m]))
+        npk.append(max(1, int(round(int(params["n_pkg"][m]) * package_scale))))
+        seeds.append(int(params["seed"][m]))
+    b.set_models(n_sh, src, scale, npk, seeds, np.concatenate(r_all), np.concatenate(rho_all))
+    return b

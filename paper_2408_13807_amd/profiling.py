@@ -1,0 +1,118 @@
+"""Profiling helpers for the IRE tracer.
+
+    python -m paper_2408_13807_amd.profiling valu-cases OUT.json
+        one-lane FP32 runs of several clouds (run it under
+        `rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_WAVES`);
+        writes their event counts in dispatch order
+    python -m paper_2408_13807_amd.profiling valu-fit DB OUT.json
+        least-squares fit of SQ_INSTS_VALU = c0 + sum_e c_e n_e over those
+        dispatches: the VALU instructions one lane executes per event type
+    python -m paper_2408_13807_amd.profiling summary DB [DB ...]
+        markdown summary of rocprofv3 databases (kernel statistics and counters)
+"""
+from __future__ import annotations
+
+import json
+import sqlite3
+import sys
+
+import numpy as np
+
+EVENTS = ("n_cross", "n_launch", "n_scat", "n_abs")
+
+
+def valu_cases() -> list[dict]:
+    from paper_2408_13807_amd import ire, workloads as wl
+    scat = dict(wl.cfg_external_small())
+    scat["albedo"] = np.full(64, 0.9)
+    cases = [("ext50", wl.cfg_external_small(), dict(n_ext=2000)),
+             ("ext101", wl.cfg_external_large(), dict(n_ext=1000)),
+             ("central200", wl.cfg_central(), dict(n_ps=200)),
+             ("gray_abs", wl.gray_model(20, 5.0, external=True), dict(n_ext=2000)),
+             ("scat_heavy", scat, dict(n_ext=500)),
+             ("ext50_short", wl.cfg_external_small(), dict(n_ext=200))]
+    out = []
+    for name, m, kw in cases:
+        r = ire.run_model(m, seed=1, max_lanes=1, **kw)
+        out.append(dict(name=name, **{k: r["stats"][k] for k in EVENTS}))
+    return out
+
+
+def _counters(db: str) -> list[dict]:
+    con = sqlite3.connect(db)
+    rows = con.execute("select dispatch_id, kernel_name, counter_name, value from counters_collection "
+                       "order by dispatch_id").fetchall()
+    per = {}
+    names = {}
+    for d, k, c, v in rows:
+        per.setdefault(d, {})[c] = v
+        names[d] = k
+    return [dict(kernel=names[d], **per[d]) for d in sorted(per)]
+
+
+def valu_fit(db: str, cases: list[dict]) -> dict:
+    disp = [c for c in _counters(db) if "ire_trace" in c["kernel"]]
+    if len(disp) != len(cases):
+        raise ValueError(f"{len(disp)} tracer dispatches but {len(cases)} cases")
+    X = np.array([[1.0] + [c[e] for e in EVENTS] for c in cases])
+    y = np.array([d["SQ_INSTS_VALU"] for d in disp])
+    coef = np.linalg.lstsq(X, y, rcond=None)[0]
+    resid = (X @ coef - y) / y
+    return {"per_lane_valu": {e[2:]: float(c) for e, c in zip(EVENTS, coef[1:])},
+            "constant": float(coef[0]), "max_rel_residual": float(np.max(np.abs(resid))),
+            "cases": [dict(c, SQ_INSTS_VALU=d["SQ_INSTS_VALU"]) for c, d in zip(cases, disp)]}
+
+
+def summary(dbs: list[str]) -> str:
+    lines = []
+    for db in dbs:
+        con = sqlite3.connect(db)
+        lines.append(f"### {db}\n")
+        try:
+            rows = con.execute("select name, total_calls, total_duration, average, percentage "
+                               "from top_kernels").fetchall()
+        except sqlite3.Error:
+            rows = []
+        if rows:
+            lines.append("| kernel | calls | total (us) | average (us) | % |")
+            lines.append("|---|---|---|---|---|")
+            for name, calls, tot, avg, pct in rows:
+                lines.append(f"| `{name[:90]}` | {calls} | {tot / 1e3:.1f} | {avg / 1e3:.1f} | {pct:.2f} |")
+            lines.append("")
+        cnt = _counters(db)
+        if cnt:
+            keys = sorted({k for c in cnt for k in c if k != "kernel"})
+            lines.append("| dispatch kernel | " + " | ".join(keys) + " |")
+            lines.append("|---|" + "---|" * len(keys))
+            for c in cnt:
+                if "ire_" not in c["kernel"]:
+                    continue
+                lines.append(f"| `{c['kernel'][:60]}` | " + " | ".join(f"{c.get(k, float('nan')):.6g}" for k in keys) + " |")
+            lines.append("")
+    return "\n".join(lines)
+
+
+def main(argv: list[str]) -> int:
+    if not argv:
+        print(__doc__)
+        return 1
+    cmd = argv[0]
+    if cmd == "valu-cases":
+        res = valu_cases()
+        with open(argv[1], "w") as f:
+            json.dump(res, f, indent=1)
+        print(json.dumps(res))
+    elif cmd == "valu-fit":
+        with open(argv[2]) as f:
+            cases = json.load(f)
+        print(json.dumps(valu_fit(argv[1], cases), indent=1))
+    elif cmd == "summary":
+        print(summary(argv[1:]))
+    else:
+        print(__doc__)
+        return 1
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main(sys.argv[1:]))

@@ -23,7 +23,8 @@ def test_library_exports_every_declared_symbol():
     assert len(names) >= 18
     for name in names:
         assert hasattr(lib, name), name
-    assert sorted(ire.EXPORTS) == names
+    from paper_2408_13807_amd import surrogate
+    assert sorted(ire.EXPORTS + surrogate.EXPORTS) == names
 
 
 def test_options_layout_and_defaults():

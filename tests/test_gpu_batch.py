@@ -1,0 +1,139 @@
+"""Batched persistent launch (ire_batch_*): parity with single-model runs and
+with the oracle, energy bookkeeping, HIP-graph replays and the autotuner."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2408_13807_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ire():
+    from paper_2408_13807_amd import ire as lib
+    return lib
+
+
+@pytest.fixture(scope="module")
+def params():
+    return wl.batch_parameters(4096, seed=3)
+
+
+def pick(params, count, tau_max=30.0, seed=0):
+    """A reproducible subsample of the study's models (cheap ones for the oracle)."""
+    rng = np.random.default_rng(seed)
+    ok = np.nonzero(params["tau_V"] < tau_max)[0]
+    return sorted(rng.choice(ok, size=count, replace=False).tolist())
+
+
+def split(b, arr):
+    return [arr[b.offsets[j]:b.offsets[j + 1]] for j in range(len(b.offsets) - 1)]
+
+
+def within(T, runs, frac=0.95):
+    """T of one run against an ensemble of runs: within max(1 %, 3 sigma) for
+    `frac` of the shells, and within max(1 %, 5 sigma, ensemble range) for all
+    (rarely hit inner shells have a discrete, often degenerate, spread)."""
+    mean, std = runs.mean(axis=0), runs.std(axis=0, ddof=1)
+    rng = runs.max(axis=0) - runs.min(axis=0)
+    d = np.abs(T - mean)
+    ok3 = d <= np.maximum(0.01 * mean, 3 * std)
+    ok5 = d <= np.maximum(np.maximum(0.01 * mean, 5 * std), rng)
+    return ok3.mean() >= frac and ok5.all(), ok3.mean()
+
+
+def test_batch_matches_single_model_ensembles(ire, params):
+    models = pick(params, 24, seed=1)
+    scale = 0.02
+    b = ire.batch_from_workloads(params, models, package_scale=scale)
+    b.run()
+    r = b.results()
+    s = r["stats"]
+    assert s["n_models"] == 24 and s["n_launch"] == sum(max(1, round(int(params["n_pkg"][m]) * scale)) for m in models)
+    assert abs((s["escaped"] + s["ffi_escaped"] + s["terminated"]) / s["L_total"] - 1) < 1e-9
+    fracs = []
+    for j, (m, T) in enumerate(zip(models, split(b, r["T"]))):
+        mm = wl.batch_model(params, m)
+        key = "n_ps" if params["central"][m] else "n_ext"
+        npk = max(1, round(int(params["n_pkg"][m]) * scale))
+        runs = np.stack([ire.run_model(mm, seed=100 + k, **{key: npk})["T"] for k in range(12)])
+        ok, f = within(T, runs)
+        fracs.append(f)
+        assert ok, (m, f)
+    print(f"batch vs single-model ensembles: min {min(fracs) * 100:.1f}% of shells within max(1%, 3 sigma)")
+    b.close()
+
+
+def test_batch_matches_oracle(ire, params):
+    models = pick(params, 4, tau_max=3.0, seed=2)
+    scale = 0.01
+    b = ire.batch_from_workloads(params, models, package_scale=scale)
+    b.run()
+    r = b.results()
+    for m, T in zip(models, split(b, r["T"])):
+        mm = wl.batch_model(params, m)
+        key = "n_ps" if params["central"][m] else "n_ext"
+        npk = max(1, round(int(params["n_pkg"][m]) * scale))
+        e = oracle.ensemble(mm, seeds=range(1, 17), **{key: npk})
+        ok, f = within(T, e["T"])
+        print(f"model {m}: {f * 100:.1f}% of shells within max(1%, 3 sigma) of the oracle")
+        assert ok
+    b.close()
+
+
+def test_batch_graph_replays(ire, params):
+    import torch
+    models = pick(params, 16, seed=3)
+    b = ire.batch_from_workloads(params, models, package_scale=0.01)
+    b.set_options(use_graph=0)
+    b.run()
+    eager = b.results()
+    b.set_options(use_graph=1)
+    for rep in range(3):
+        b.run()
+        r = b.results()
+        s = r["stats"]
+        assert s["n_launch"] == eager["stats"]["n_launch"]
+        assert abs((s["escaped"] + s["ffi_escaped"] + s["terminated"]) / s["L_total"] - 1) < 1e-9
+        # replays start from zero: the same mean temperature level as the eager run
+        ratio = r["T"] / eager["T"]
+        assert abs(np.median(ratio) - 1) < 0.01
+        # eager work and a synchronisation between replays
+        x = torch.ones(1 << 20, device="cuda")
+        torch.cuda.synchronize()
+        assert float(x.sum()) == float(1 << 20)
+    b.close()
+
+
+def test_batch_autotune_and_cache(ire, params, tmp_path):
+    models = pick(params, 32, seed=4)
+    b = ire.batch_from_workloads(params, models, package_scale=0.02)
+    cache = str(tmp_path / "ire_autotune.json")
+    o = b.autotune(fraction=0.2, cache_path=cache)
+    assert o["batch"] in (16, 24, 32, 48) and o["item_packages"] in (16384, 65536, 262144)
+    assert os.path.exists(cache) and "item_packages" in open(cache).read()
+    o2 = b.autotune(fraction=0.2, cache_path=cache)     # reused from the cache
+    assert (o2["batch"], o2["item_packages"]) == (o["batch"], o["item_packages"])
+    b.run()
+    r = b.results()
+    assert r["stats"]["n_models"] == 32
+    b.close()
+
+
+def test_batch_rejects_invalid(ire, params):
+    with ire.IREBatch(0) as b:
+        with pytest.raises(ire.IREError) as e:
+            b.run()
+        assert e.value.code == ire.IRE_E_STATE
+        d = wl.synthetic_dust()
+        b.set_dust(d["nu"], d["kabs"], d["albedo"], d["g"])
+        with pytest.raises(ire.IREError) as e:   # external model but no J shape
+            b.set_models([3], [ire.IRE_SRC_EXTERNAL], [1.0], [100], [1], [0.0, 1.0, 2.0, 3.0], [1.0, 1.0, 1.0])
+        assert e.value.code == ire.IRE_E_STATE
+        b.set_sources(wl.isrf(d["nu"]), None)
+        with pytest.raises(ire.IREError) as e:   # radii not increasing
+            b.set_models([3], [ire.IRE_SRC_EXTERNAL], [1.0], [100], [1], [0.0, 1.0, 1.0, 3.0], [1.0, 1.0, 1.0])
+        assert e.value.code == ire.IRE_E_INVALID

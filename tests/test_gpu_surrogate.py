@@ -1,0 +1,94 @@
+"""BF16-MFMA surrogate kernels: gradients against the FP64 CPU reference,
+training, ensemble prediction, save/load, and graph-replayed training."""
+import numpy as np
+import pytest
+
+from oracle import mlp_ref
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sur():
+    from paper_2408_13807_amd import surrogate
+    return surrogate
+
+
+def _data(n, seed=0):
+    rng = np.random.default_rng(seed)
+    X = np.column_stack([rng.uniform(-1, 3, n), rng.uniform(0, 2, n), rng.uniform(-1, 2, n),
+                         rng.uniform(-1, 2, n), rng.integers(0, 2, n), rng.uniform(0, 1, n)]).astype(np.float32)
+    y = (1.2 + 0.3 * np.sin(X[:, 0]) - 0.2 * X[:, 5] * X[:, 1] + 0.1 * X[:, 4]).astype(np.float32)
+    return X, y
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+@pytest.mark.parametrize("depth", [1, 4])
+def test_gradients_match_fp64_reference(sur, depth):
+    net = sur.SurNet(members=2, depth=depth, seed=3)
+    X, y = _data(1000, seed=1)
+    xm, xs = X.mean(axis=0), X.std(axis=0)
+    ym, ys = float(y.mean()), float(y.std())
+    net.set_normalization(xm, xs, ym, ys)
+    P = net.get_params()
+    loss, G = net.gradients(X, y)
+    for m in range(2):
+        lr, gr = mlp_ref.loss_and_grad(P[m].astype(np.float64), depth, X, y, xm, xs, ym, ys)
+        assert abs(loss[m] / lr - 1) < 2e-2, (loss[m], lr)
+        # block by block: BF16 operands with FP32 accumulation against FP64
+        o = 0
+        blocks = [256 * 32] + [256 * 256] * (depth - 1) + [256] * depth + [256, 1]
+        for k, size in enumerate(blocks):
+            e = _rel(G[m, o:o + size].astype(np.float64), gr[o:o + size])
+            assert e < 5e-2, (m, k, e)
+            o += size
+        cos = G[m] @ gr / (np.linalg.norm(G[m]) * np.linalg.norm(gr))
+        assert cos > 0.999
+    net.close()
+
+
+def test_prediction_matches_reference_forward(sur):
+    net = sur.SurNet(members=3, depth=4, seed=5)
+    X, y = _data(3000, seed=2)
+    xm, xs = X.mean(axis=0), X.std(axis=0)
+    net.set_normalization(xm, xs, 1.2, 0.25)
+    P = net.get_params()
+    mean, spread = net.predict(X)
+    ref = np.stack([mlp_ref.predict_logT(P[m].astype(np.float64), 4, X, xm, xs, 1.2, 0.25) for m in range(3)])
+    assert np.max(np.abs(mean - ref.mean(axis=0))) < 2e-2
+    T = 10.0 ** ref
+    sp = T.std(axis=0, ddof=1) / T.mean(axis=0)
+    assert np.max(np.abs(spread - sp)) < 5e-3 + 0.05 * sp.max()
+    net.close()
+
+
+@pytest.mark.parametrize("use_graph", [1, 0])
+def test_training_reduces_loss(sur, use_graph):
+    X, y = _data(50_000, seed=3)
+    net = sur.SurNet(members=2, depth=4, seed=7)
+    loss0, _ = net.gradients(X[:4096], y[:4096])
+    loss = net.train(X, y, steps=300, batch=1024, lr=2e-3, use_graph=use_graph)
+    assert np.all(loss < 0.05 * loss0), (loss0, loss)
+    Xt, yt = _data(5000, seed=4)
+    mean, spread = net.predict(Xt)
+    assert np.sqrt(np.mean((mean - yt) ** 2)) < 0.05
+    net.close()
+
+
+def test_save_load_roundtrip(sur, tmp_path):
+    net = sur.SurNet(members=2, depth=2, seed=9)
+    X, y = _data(2000, seed=5)
+    net.train(X, y, steps=20, batch=512)
+    path = str(tmp_path / "net.sur")
+    net.save(path)
+    a = net.predict(X)
+    other = sur.SurNet(members=2, depth=2, seed=10)
+    other.load(path)
+    b = other.predict(X)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+    net.close()
+    other.close()

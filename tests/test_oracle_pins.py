@@ -400,3 +400,21 @@ def test_rejects_invalid(orc):
         orc.run(dict(m, r_edges=bad), n_ext=10)
     with pytest.raises(ValueError):
         orc.run(dict(m, J=None), n_ext=10)
+
+
+@pytest.mark.parametrize("n,tau,p", [(3, 30.0, 1.0), (5, 100.0, 1.5)])
+def test_whole_method_against_brute_force(orc, n, tau, p):
+    # a purely absorbing cloud heated by its central source, re-emission spread
+    # uniformly over each shell: the IRE equilibrium is the fixed point of the
+    # deterministic transfer equations solved by dense quadrature
+    from oracle import bruteforce as bf
+    m = wl.central_source(n=n, tau_V=tau, p=p, r_in=10 * wl.AU)
+    m["albedo"] = np.zeros(64)
+    ref = bf.solve_central(m)
+    e = orc.ensemble(m, n_ps=400_000, seeds=range(1, 9), reemit_uniform=1)
+    mean = e["T"].mean(axis=0)
+    sem = e["T"].std(axis=0, ddof=1) / math.sqrt(8)
+    assert np.all(np.abs(mean - ref["T"]) <= 4.5 * sem + 2e-4 * ref["T"]), (mean, ref["T"], sem)
+    # energy: every package leaves, so the escaped power equals the source power
+    s = e["stats"][0]
+    assert abs(sum(s["escaped"]) / s["L_ps"] - 1) < 1e-10
