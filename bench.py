@@ -42,6 +42,9 @@ WORKLOADS = {
                                "central 5000 K 1 Lsun source, 200 log shells 10 AU-0.1 pc, tau_V=100, 1e8 packages"),
     "ext50_tauV1_1e5": ("cfg_external_small", 100_000,
                         "external sphere, 50 equal shells, central tau_V=1, 1e5 packages"),
+    "batch4096": ("batch_parameters", None,
+                  "batched study: 4096 models, shells U{20..400}, tau_V logU(0.1,1000), density exponent U(0,2), "
+                  "external or central source, packages logU(1e5,1e7), one persistent launch"),
 }
 
 
@@ -63,6 +66,65 @@ def cpu_baseline(model: dict, key: str, n_pkg_per_seed: int, seeds: int, steppin
                       f"serial FP64 oracle, {threads} threads, {dt:.1f} s wall ({stepping_note})"}
 
 
+def bench_batch(args) -> dict:
+    """Models/s of the batched study in one persistent launch (HIP-graph replay),
+    against per-model launches of a random sample of the same models."""
+    import numpy as np
+    import torch
+
+    from paper_2408_13807_amd import ire, workloads
+
+    scale = float(os.environ.get("IRE_BENCH_BATCH_SCALE", "1.0"))
+    params = workloads.batch_parameters(4096, seed=3)
+    torch.cuda.set_device(0)
+    b = ire.batch_from_workloads(params, package_scale=scale)
+    n_pkg = int(sum(max(1, round(int(x) * scale)) for x in params["n_pkg"]))
+    for w in range(args.warmup):
+        b.run()
+        b.results(allow_limit=True)
+    ms, ev = [], None
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        b.run()
+        st = b.results(allow_limit=True)["stats"]
+        ms.append(st["ms_run"])
+        ev = st if ev is None else {k: ev[k] + st[k] for k in ("n_cross", "n_launch", "n_scat", "n_abs")}
+    t1 = time.perf_counter()
+    b.close()
+    # per-model launches of a sample of the same models (same budgets)
+    rng = np.random.default_rng(0)
+    sample = rng.choice(4096, 64, replace=False)
+    t_single = 0.0
+    for m in sample:
+        mm = workloads.batch_model(params, int(m))
+        key = "n_ps" if params["central"][m] else "n_ext"
+        npk = max(1, round(int(params["n_pkg"][m]) * scale))
+        ts = time.perf_counter()
+        ire.run_model(mm, seed=int(params["seed"][m]) & 0xFFFFFFFF, allow_limit=True, **{key: npk})
+        t_single += time.perf_counter() - ts
+    single_models_per_s = len(sample) / t_single
+    k_ms = sum(ms) / len(ms)
+    per_launch = {k: ev[k] / args.steps for k in ("n_cross", "n_launch", "n_scat", "n_abs")}
+    achieved = algorithmic_ops(per_launch) / (k_ms * 1e-3) / 1e12
+    value = 4096 * args.steps / (t1 - t0)
+    return {
+        "metric": "models/s (IRE, batched parameter study in one persistent launch)",
+        "value": value, "unit": "models/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": (t1 - t0) * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": WORKLOADS["batch4096"][2], "models": 4096, "packages": n_pkg,
+                   "package_scale": scale, "stepping": "fp32", "accumulators": "fp64"},
+        "packages_per_s": n_pkg * args.steps / (t1 - t0),
+        "device_ms_avg": k_ms,
+        "events_per_launch": per_launch,
+        "per_model_launch_models_per_s": single_models_per_s,
+        "per_model_sample": "64 random models of the study, one ire_run each, same package budgets",
+        "speedup_vs_per_model": value / single_models_per_s,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
+                     "unit": "TOP/s (VALU lane-instructions)", "frac": achieved / VALU_PEAK_TOPS, "traffic": None},
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +137,10 @@ def main() -> int:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
               file=sys.stderr)
         return 2
+
+    if args.workload == "batch4096":
+        print(json.dumps(bench_batch(args)), flush=True)
+        return 0
 
     import torch
 
@@ -91,7 +157,7 @@ def main() -> int:
 
     h = ire.IREModel(0)
     h.set_model(model)
-    h.set_options(batch=int(os.environ.get("IRE_BENCH_BATCH", "0")))
+    h.set_options(batch=int(os.environ.get("IRE_BENCH_BATCH", "0")), aggregate=int(os.environ.get("IRE_BENCH_AGG", "1")))
 
     def step(seed: int):
         h.run(seed=seed, stream=stream, **{key: n_pkg})

@@ -260,6 +260,27 @@ int sur_predict(sur_net *s, const float *X, int64_t n, float *mean_logT, float *
 /* Same on device pointers, asynchronous on hip_stream. */
 int sur_predict_dev(sur_net *s, const float *X_dev, int64_t n, float *mean_logT_dev, float *spread_dev,
                     void *hip_stream);
+/* Ensemble prediction for whole cloud models.  Model m owns output rows
+ * [row_off[m], row_off[m+1]) (row_off[0] = 0, non-decreasing); its cloud
+ * parameters are model_x[5m .. 5m+4] (the first five surrogate inputs: log10
+ * tau_V, density exponent, log10 L/L_sun, log10 field scale, source type) and
+ * its shells' relative mid-radii r_mid/R_out are radius[radius_off[m] + j],
+ * j < row_off[m+1] - row_off[m] (models with the same shell grid may share
+ * radius values; radius[n_radius]).  Writes mean log10 T and the spread
+ * std(T)/mean(T) per row, and, when model_spread is not NULL, the largest row
+ * spread of every model (model_spread[n_models]) for the choice of models to
+ * re-run with the tracer.  Host arrays; offsets are validated (IRE_E_INVALID). */
+int sur_predict_models(sur_net *s, int64_t n_models, const float *model_x, const int64_t *row_off,
+                       const int64_t *radius_off, const float *radius, int64_t n_radius, float *mean_logT,
+                       float *spread, float *model_spread);
+/* Same on device pointers, asynchronous on hip_stream; n_rows = row_off[n_models]
+ * is passed by the caller.  Offsets are not validated on the host; the kernels
+ * keep every access inside the given arrays (a radius index outside
+ * [0, n_radius) reads 0). */
+int sur_predict_models_dev(sur_net *s, int64_t n_models, int64_t n_rows, const float *model_x_dev,
+                           const int64_t *row_off_dev, const int64_t *radius_off_dev, const float *radius_dev,
+                           int64_t n_radius, float *mean_logT_dev, float *spread_dev, float *model_spread_dev,
+                           void *hip_stream);
 int sur_save(sur_net *s, const char *path);
 int sur_load(sur_net *s, const char *path);
 const char *sur_last_error(const sur_net *s);

@@ -2,7 +2,9 @@
 
 TEST INFRASTRUCTURE ONLY (called by tests to check the GPU kernels).  Written
 from the definition of the network, with back-propagation by hand:
-    x' = (x - x_mean) / x_std, padded with zeros to 32 inputs,
+    x' = (x - x_mean) / x_std for the 6 features, then the derived input
+         log10(max(x_5, 1e-4)) + 1.5 (x_5 = r / R_out, unnormalised), then
+         zeros up to 32 inputs,
     h_0 = SiLU(W_0 x' + b_0),  h_l = SiLU(W_l h_{l-1} + b_l)  (l = 1 .. depth-1),
     out = w_out . h_{depth-1} + b_out,
     loss = mean over rows of (out - (y - y_mean) / y_std)^2,
@@ -46,6 +48,7 @@ def inputs(X, x_mean, x_std):
     xs = (X - np.asarray(x_mean, np.float64)) / np.asarray(x_std, np.float64)
     out = np.zeros((len(X), N_IN))
     out[:, :N_FEAT] = xs
+    out[:, N_FEAT] = np.log10(np.maximum(X[:, N_FEAT - 1], 1e-4)) + 1.5
     return out
 
 

@@ -345,13 +345,14 @@ int ire_advance(ire_model *m, uint64_t n_ext, uint64_t n_ps, void *hip_stream) {
     if ((e = hipSetDevice(m->device)) != hipSuccess) return m->hip_fail(e, "hipSetDevice");
     const int n = (int)m->rho.size(), K = (int)m->nu.size();
     const int fp64 = m->opt.stepping == IRE_FP64;
+    // packages per lane: one for FP64 and for runs with a cap on packages in flight
     size_t lds = 0;
     int block, grid;
     if (fp64) {
         block = 256;
         grid = m->n_cu * 8;
     } else {
-        lds = ire::trace_lds_bytes(n + (m->r_edges[0] > 0.0 ? 1 : 0) + 1, K, m->n_t);
+        lds = ire::trace_lds_bytes(n + (m->r_edges[0] > 0.0 ? 1 : 0) + ire::kSentinels, K, m->n_t);
         if (lds > m->max_lds)
             return m->fail(IRE_E_INVALID, "FP32 tables need %zu bytes of LDS, the device has %zu; use IRE_FP64",
                            lds, m->max_lds);

@@ -138,7 +138,7 @@ int prepare(ire_batch *b) {
         dm.seed = md.seed;
         b->L_total += L;
         b->mdev.push_back(dm);
-        b->max_table = std::max(b->max_table, n + dm.cav + 1);
+        b->max_table = std::max(b->max_table, n + dm.cav + ire::kSentinels);
         // cost per package: shells crossed per flight times (1 + extinction depth at the median frequency)
         const int km = kmed[md.source == IRE_SRC_EXTERNAL ? 0 : 1];
         const double kext = b->kabs[km] / (1.0 - b->albedo[km]);
@@ -218,7 +218,8 @@ int enqueue(ire_batch *b, hipStream_t s) {
     hipError_t e;
     if ((e = ire::launch_zero_batch(b->A.p, b->n_shells, b->stats.p, s)) != hipSuccess) return b->hip_fail(e, "zero");
     const int grid = std::max(1, std::min(b->n_cu, p.n_items));
-    if ((e = ire::launch_trace_batch(p, b->opt.aggregate, grid, lds, s)) != hipSuccess) return b->hip_fail(e, "trace");
+    if ((e = ire::launch_trace_batch(p, b->opt.aggregate, grid, lds, s)) != hipSuccess)
+        return b->hip_fail(e, "trace");
     ire::BatchFinalizeParams f{};
     f.n_shells = (int)b->n_shells;
     f.n_t = b->n_t;
@@ -243,7 +244,8 @@ int run_on(ire_batch *b, hipStream_t s) {
         int rc = prepare(b);
         if (rc) return rc;
     }
-    if ((e = ire::batch_configure(b->opt.aggregate, lds_bytes(b))) != hipSuccess) return b->hip_fail(e, "configure");
+    if ((e = ire::batch_configure(b->opt.aggregate, lds_bytes(b))) != hipSuccess)
+        return b->hip_fail(e, "configure");
     if ((e = hipEventRecord(b->ev0, s)) != hipSuccess) return b->hip_fail(e, "event");
     if (b->opt.use_graph) {
         if (!b->exec) {

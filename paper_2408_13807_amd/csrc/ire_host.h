@@ -112,8 +112,8 @@ inline void build_shell_table(const double *r_edges, const double *rho, int n, s
     const double Rout = r_edges[n];
     const int cav = r_edges[0] > 0.0 ? 1 : 0;
     const size_t base_f = shf.size(), base_d = shd.size();
-    shf.resize(base_f + n + cav + 1);
-    shd.resize(base_d + n + cav + 1);
+    shf.resize(base_f + n + cav + kSentinels);
+    shd.resize(base_d + n + cav + kSentinels);
     if (cav) {
         const double a = r_edges[0] / Rout;
         shd[base_d] = ShellD{0.0, a * a, 0.0, 0.0};
@@ -131,8 +131,10 @@ inline void build_shell_table(const double *r_edges, const double *rho, int n, s
     // the outermost edge is exactly 1 in both precisions
     shd[base_d + cav + n - 1].r2_out = 1.0;
     shf[base_f + cav + n - 1].r2_out = 1.0f;
-    shd[base_d + cav + n] = ShellD{1.0, 4.0, HUGE_VAL, 0.0};
-    shf[base_f + cav + n] = ShellF{1.0f, 4.0f, HUGE_VALF, 0.0f};
+    for (int j = 0; j < kSentinels; ++j) {
+        shd[base_d + cav + n + j] = ShellD{1.0, 4.0, HUGE_VAL, 0.0};
+        shf[base_f + cav + n + j] = ShellF{1.0f, 4.0f, HUGE_VALF, 0.0f};
+    }
 }
 
 // Device buffer that grows on demand.

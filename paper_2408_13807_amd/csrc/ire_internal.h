@@ -9,6 +9,10 @@ namespace ire {
 // Absorbed-energy accumulators are FP64, one per shell, each on its own
 // 128-byte line so that returning atomics on different shells never share a line.
 constexpr int kAccStride = 16;
+// Shell tables end in two sentinel records beyond the surface (infinite
+// density): a flight that leaves the cloud ends in the first; the second keeps
+// the tracer's one-record-ahead reads inside the table for every lane.
+constexpr int kSentinels = 2;
 
 // Shell geometry in units of the outer radius: squared inner and outer radius,
 // density times the outer radius (so kappa * rho_hat * l_hat is an optical depth

@@ -141,17 +141,26 @@ __device__ __forceinline__ double wave_excl_scan(double v) {
 }
 
 // Returning fetch-add of E into A[i] for the lanes with act set; every lane of
-// the wave must call it.  With AGG, lanes that hit the same shell are folded
-// into one atomic and each receives base + (sum of E of lower lanes).
+// the wave must call it.  Each lane receives the value of A[i] just before its
+// own deposit.  With AGG, the lanes that hit the same shell are folded into one
+// deposit by their lowest lane (the group leader), and each member receives the
+// leader's base plus the energy of the lower lanes of its group.  The groups are
+// formed with ballots and shuffles first, so that the leaders of all groups
+// then issue their atomics as one instruction: one round trip to L2 per call,
+// however many shells the wave hits.
 template <bool AGG>
 __device__ __forceinline__ double fetch_add_energy(double *A, int i, double E, bool act) {
-    double res = 0.0;
     if constexpr (!AGG) {
+        double res = 0.0;
         if (act) res = unsafeAtomicAdd(&A[(size_t)i * kAccStride], E);
         return res;
     } else {
         const int lane = __lane_id();
         unsigned long long pending = __ballot(act);
+        double dep = 0.0;     // the leader's deposit: its group's total energy
+        double ex = 0.0;      // energy of the lower lanes of this lane's group
+        int leader_of = lane;
+        bool lead = false;
         while (pending) {
             const int leader = __ffsll((long long)pending) - 1;
             const int s = __shfl(i, leader, kWave);
@@ -159,18 +168,28 @@ __device__ __forceinline__ double fetch_add_energy(double *A, int i, double E, b
             pending &= ~grp;
             const bool mine = (grp >> lane) & 1ull;
             if (__popcll(grp) == 1) {
-                if (mine) res = unsafeAtomicAdd(&A[(size_t)s * kAccStride], E);
+                if (mine) {
+                    dep = E;
+                    lead = true;
+                }
             } else {
                 const double v = mine ? E : 0.0;
-                const double ex = wave_excl_scan(v);
-                const double tot = __shfl(ex + v, kWave - 1, kWave);
-                double base = 0.0;
-                if (lane == leader) base = unsafeAtomicAdd(&A[(size_t)s * kAccStride], tot);
-                base = __shfl(base, leader, kWave);
-                if (mine) res = base + ex;
+                const double e = wave_excl_scan(v);
+                const double tot = __shfl(e + v, kWave - 1, kWave);
+                if (mine) {
+                    ex = e;
+                    leader_of = leader;
+                }
+                if (lane == leader) {
+                    dep = tot;
+                    lead = true;
+                }
             }
         }
-        return res;
+        double base = 0.0;
+        if (lead) base = unsafeAtomicAdd(&A[(size_t)i * kAccStride], dep);
+        base = __shfl(base, leader_of, kWave);
+        return act ? base + ex : 0.0;
     }
 }
 
@@ -245,246 +264,281 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
 
     unsigned long long pool_next = 0, pool_end = 0;  // wave-uniform
 
-    // package state
+    // package state, one package per lane
     int st = lane_off ? ST_DONE : ST_DEAD;
-    const Shell *ps = sh;   // current shell
+    const Shell *ps = sh;          // current shell
+    Shell cur = P<R>::shell(sh);   // its record, kept in registers while the package flies
     int k = 0, src = 0;
     R b2 = 0, t = 0, W = 1, W0 = 1;
-    R sig = 0;          // column (rho-weighted length) left before the next interaction
-    double eps = 0.0;   // package energy of the lane's source
-    bool ev_abs = false; // that interaction is an absorption (else a scattering)
+    R sig = 0;                     // column (rho-weighted length) left before the next interaction
+    double eps = 0.0;              // package energy of the package's source
+    bool ev_abs = false;           // that interaction is an absorption (else a scattering)
     uint32_t pid_lo = 0, pid_hi = 0, blk = 0;
     unsigned long long events = 0;
 
+    // One boundary step of a package in flight (Eq. 4), computed for every
+    // lane and committed only where the package is in flight.  Both free
+    // paths fall by kappa rho l along a flight, so the one that runs out
+    // first is fixed when they are drawn: the flight carries the smaller of
+    // tau_A / kappa_A and tau_S / kappa_S as a column of rho-weighted length
+    // and the type of its interaction.  The shell a crossing leads into is
+    // known before the crossing is computed (inward while the ray approaches
+    // its tangent point inside the inner sphere, outward otherwise), so its
+    // record is requested first and its LDS latency overlaps the arithmetic.
+    // A package that does not cross parks with t and sig unchanged; the event
+    // pass moves it to the interaction point.
+    auto step = [&]() {
+        const bool f = st == ST_FLY;
+        const bool inward = (t < (R)0) && (b2 < cur.r2_in);
+        const Shell *const pn = inward ? ps - 1 : ps + 1;
+        const Shell nx = P<R>::shell(pn);
+        const R arg = (inward ? cur.r2_in : cur.r2_out) - b2;
+        const R sq = P<R>::sqrt_(arg > (R)0 ? arg : (R)0);
+        const R tn = inward ? -sq : sq;
+        const R ds = cur.rho * (tn - t);
+        const bool cross = ds < sig;
+        const bool mv = f && cross;
+        sig = mv ? sig - ds : sig;
+        t = mv ? tn : t;
+        ps = mv ? pn : ps;
+        lc.cross += mv ? 1u : 0u;
+        st = (f && !cross) ? (int)ST_EVT : st;
+        // keep the compiler from hoisting the use of the record (and with it
+        // the wait for its LDS read) above the step's arithmetic
+        __builtin_amdgcn_sched_barrier(0);
+        cur.r2_in = mv ? nx.r2_in : cur.r2_in;
+        cur.r2_out = mv ? nx.r2_out : cur.r2_out;
+        cur.rho = mv ? nx.rho : cur.rho;
+        cur.inv_rho = mv ? nx.inv_rho : cur.inv_rho;
+    };
+
+    // The event pass: escapes, the event-count limit, refills from the wave's
+    // package pool, launches, scatterings and absorptions with immediate
+    // re-emission, then new free paths.
+    auto event_pass = [&]() {
+            // ---- event batch
+            const int i = (int)(ps - sh);        // internal shell index
+            bool absorbing = false, scattering = false;
+            // a parked package still stands where its last step began: move it
+            // along the column left to the interaction point
+            if (st == ST_EVT) t += sig * cur.inv_rho;
+            if (st == ST_EVT) {
+                if (ps == sentinel) {
+                    // the flight left the cloud (the step into the sentinel is no crossing)
+                    const double e = eps * (double)W;
+                    if (src == 0) lc.esc0 += e; else lc.esc1 += e;
+                    lc.escape++;
+                    lc.cross--;
+                    if (events == 0) lc.direct++;
+                    st = ST_DEAD;
+                } else if (events >= o.max_events) {
+                    lc.term += eps * (double)W;
+                    lc.limit++;
+                    st = ST_DEAD;
+                } else {
+                    events++;
+                    absorbing = ev_abs;
+                    scattering = !ev_abs;
+                }
+            }
+
+            // refill lanes without a package from the wave-private pool, which takes
+            // `chunk` package indices from the global cursor at a time
+            bool launching = false;
+            const unsigned long long need = __ballot(st == ST_DEAD);
+            if (need) {
+                const unsigned long long cnt = __popcll(need);
+                const unsigned long long avail = pool_end - pool_next;
+                unsigned long long fresh = 0;
+                if (avail < cnt) {
+                    const int leader = __ffsll((long long)need) - 1;
+                    if (lane == leader) fresh = atomicAdd(cursor, chunk);
+                    fresh = __shfl(fresh, leader, kWave);
+                }
+                if (st == ST_DEAD) {
+                    const unsigned long long rank = __popcll(need & __lanemask_lt());
+                    const unsigned long long gidx = rank < avail ? pool_next + rank : fresh + (rank - avail);
+                    if (gidx >= total) {
+                        st = ST_DONE;
+                    } else {
+                        src = gidx < mc.n_ext ? 0 : 1;
+                        const unsigned long long pid = (src ? mc.pid0[1] + (gidx - mc.n_ext) : mc.pid0[0] + gidx);
+                        eps = src ? mc.eps[1] : mc.eps[0];
+                        pid_lo = (uint32_t)pid;
+                        pid_hi = (uint32_t)(pid >> 32);
+                        blk = 0;
+                        events = 0;
+                        W = 1;
+                        launching = true;
+                    }
+                }
+                if (avail < cnt) {
+                    pool_next = fresh + (cnt - avail);
+                    pool_end = fresh + chunk;
+                } else {
+                    pool_next += cnt;
+                }
+            }
+            const bool ev = launching || absorbing || scattering;
+
+            // absorption: deposit E into the shell; A_before locates this package's
+            // slice [A_before, A_before + E] of the shell's absorbed power
+            const double E = absorbing ? eps * (double)W : 0.0;
+            const double invM = absorbing ? mc.invM[i - cav] : 0.0;   // issued before the atomic's round trip
+            double A_before = 0.0;
+            if (__ballot(absorbing)) A_before = fetch_add_energy<AGG>(mc.A, i - cav, E, absorbing);
+
+            Rand4 r1{0, 0, 0, 0}, r2b{0, 0, 0, 0};
+            if (ev) r1 = philox(blk++, pid_lo, pid_hi, (uint32_t)src, key0, key1);
+            if (absorbing) r2b = philox(blk++, pid_lo, pid_hi, (uint32_t)src, key0, key1);
+
+            // new frequency: source spectrum at launch, difference spectrum at re-emission
+            int row = 0;
+            if (absorbing) {
+                const double astar = (A_before + (((double)r1.x + 0.5) * 0x1p-32) * E) * invM;
+                row = count_le(G, n_t, (R)astar);
+                if (row > n_t - 1) { row = n_t - 1; lc.reabove++; }
+                lc.abs++;
+            }
+            if (launching || absorbing) {
+                const R *tab = launching ? cdf + src * K : D + (size_t)row * K;
+                k = min(count_le(tab, K, P<R>::uni(launching ? r1.x : r1.y)), K - 1);
+            }
+            const Dust d = dust[k];
+
+            // new direction: isotropic re-emission or Henyey-Greenstein scattering
+            if (absorbing || scattering) {
+                R r2 = b2 + t * t;
+                R rr = P<R>::sqrt_(r2);
+                R mun;
+                if (absorbing) {
+                    mun = (R)2 * P<R>::uni(r1.z) - (R)1;
+                    if (o.reemit_uniform) {
+                        const Shell s = cur;
+                        const R rin = P<R>::sqrt_(s.r2_in);
+                        const R rout = P<R>::sqrt_(s.r2_out);
+                        const R c3 = rin * rin * rin + P<R>::uni(r2b.y) * (rout * rout * rout - rin * rin * rin);
+                        rr = P<R>::cbrt_(c3);
+                        r2 = rr * rr;
+                    }
+                } else {
+                    lc.scat++;
+                    const R gg = d.g;
+                    const R mu = rr > (R)0 ? t * P<R>::rcp(rr) : (R)1;
+                    const R u0 = P<R>::uni(r1.x);
+                    R ct;
+                    if (gg > (R)-1e-6 && gg < (R)1e-6) {
+                        ct = (R)2 * u0 - (R)1;
+                    } else {
+                        const R f = ((R)1 - gg * gg) * P<R>::rcp((R)1 - gg + (R)2 * gg * u0);
+                        ct = ((R)1 + gg * gg - f * f) * P<R>::rcp((R)2 * gg);
+                        ct = ct > (R)1 ? (R)1 : (ct < (R)-1 ? (R)-1 : ct);
+                    }
+                    const R st2 = ((R)1 - ct) * ((R)1 + ct);
+                    const R sp2 = ((R)1 - mu) * ((R)1 + mu);
+                    const R sn = P<R>::sqrt_((st2 > (R)0 ? st2 : (R)0) * (sp2 > (R)0 ? sp2 : (R)0));
+                    mun = mu * ct + sn * P<R>::cos2pi(P<R>::uni(r1.y));
+                    mun = mun > (R)1 ? (R)1 : (mun < (R)-1 ? (R)-1 : mun);
+                }
+                t = rr * mun;
+                b2 = r2 * ((R)1 - mun) * ((R)1 + mun);
+            }
+
+            // both free paths are redrawn after every event (Eq. 1)
+            R tauA = P<R>::nlog(P<R>::uni(absorbing ? r1.w : r1.z));
+            R tauS = P<R>::nlog(P<R>::uni(absorbing ? r2b.x : r1.w));
+
+            // launch geometry and launch weights (Eqs. 2-3, Eq. 5, Eqs. 9-12)
+            if (launching) {
+                lc.launch++;
+                if (src == 0) {
+                    const R u1 = P<R>::uni(r1.y);
+                    R mu;
+                    if (o.k_bg == 0.5) {
+                        mu = P<R>::sqrt_(u1);
+                    } else {
+                        const R kb = (R)o.k_bg;
+                        mu = P<R>::powr(u1, kb);
+                        W = (R)2 * kb * P<R>::powr(mu, (R)2 - (R)1 / kb);
+                    }
+                    ps = sentinel - 1;
+                    t = -mu;
+                    b2 = ((R)1 - mu) * ((R)1 + mu);
+                } else {
+                    ps = sh;            // the centre (inside the cavity shell when there is one)
+                    b2 = 0;
+                    t = 0;
+                }
+                if (o.ffi) {
+                    // extinction optical depth along the whole first ray
+                    R tau0 = 0, tt = t;
+                    for (const Shell *q = ps; q != sentinel;) {
+                        const Shell s = *q;
+                        const bool inward = (tt < (R)0) && (b2 < s.r2_in);
+                        const R arg = (inward ? s.r2_in : s.r2_out) - b2;
+                        const R sq = P<R>::sqrt_(arg > (R)0 ? arg : (R)0);
+                        const R tn = inward ? -sq : sq;
+                        const R lb = tn - tt > (R)0 ? tn - tt : (R)0;
+                        tau0 += d.kext * s.rho * lb;
+                        tt = tn;
+                        q += inward ? -1 : 1;
+                    }
+                    if (!(tau0 > (R)0)) {
+                        // no matter on the ray: the package leaves untouched
+                        if (src == 0) lc.esc0 += eps * (double)W; else lc.esc1 += eps * (double)W;
+                        lc.escape++;
+                        lc.direct++;
+                        launching = false;
+                        st = ST_DEAD;
+                    } else {
+                        const R pf = -P<R>::expm1_(-tau0);
+                        lc.ffi += eps * (double)W * (double)(((R)1) - pf);
+                        W *= pf;
+                        const R tau = -P<R>::log1p_(-P<R>::uni(r1.z) * pf);
+                        if (P<R>::uni(r1.w) < d.alb) { tauS = tau * d.alb; tauA = P<R>::inf(); }
+                        else { tauA = tau * ((R)1 - d.alb); tauS = P<R>::inf(); }
+                    }
+                }
+                W0 = W;
+            }
+
+            // weight floor (Sect. 2.2.1)
+            if ((absorbing || scattering) && W < (R)o.w_floor * W0) {
+                lc.term += eps * (double)W;
+                lc.floor++;
+                st = ST_DEAD;
+            } else if (launching || absorbing || scattering) {
+                const R sA = tauA * d.inv_kA;
+                const R sS = tauS * d.inv_kS;
+                ev_abs = sA <= sS;
+                sig = ev_abs ? sA : sS;
+                st = ST_FLY;
+            }
+    };
+
     for (;;) {
-        // ---- crossing sweep.  Both free paths fall by kappa rho l along a flight
-        // (Eq. 4), so the one that runs out first is fixed when they are drawn:
-        // the flight carries the smaller of tau_A / kappa_A and tau_S / kappa_S
-        // as a column of rho-weighted length and the type of its interaction.
-        // A lane that reaches its interaction parks; the wave stops stepping
-        // when enough lanes are parked.
+        // ---- crossing sweep: packages in flight step from boundary to boundary;
+        // a package that reaches its interaction parks, and the wave stops stepping
+        // when enough of its packages are parked to process their events together.
+        // Two steps per check: a step of a parked package changes nothing.
         {
             const int live = __popcll(__ballot(st != ST_DONE));
             const int half = (live + 1) / 2;
             const int want = batch < half ? batch : (half > 0 ? half : 1);
             for (;;) {
-                const unsigned long long fly = __ballot(st == ST_FLY);
-                if (fly == 0 || live - __popcll(fly) >= want) break;
-                if (st == ST_FLY) {
-                    const Shell s = P<R>::shell(ps);
-                    const bool inward = (t < (R)0) && (b2 < s.r2_in);
-                    const R arg = (inward ? s.r2_in : s.r2_out) - b2;
-                    const R sq = P<R>::sqrt_(arg > (R)0 ? arg : (R)0);
-                    const R tn = inward ? -sq : sq;
-                    const R ds = s.rho * (tn - t);
-                    const bool cross = ds < sig;
-                    const R t_evt = t + sig * s.inv_rho;
-                    sig -= ds;
-                    t = cross ? tn : t_evt;
-                    ps += cross ? (inward ? -1 : 1) : 0;
-                    lc.cross += cross ? 1u : 0u;
-                    st = cross ? ST_FLY : ST_EVT;
-                }
+                const int nfly = __popcll(__ballot(st == ST_FLY));
+                if (nfly == 0 || live - nfly >= want) break;
+                step();
+                step();
             }
         }
-        if (__ballot(st != ST_DONE && st != ST_FLY) == 0) break;  // nothing parked: all lanes finished
+        // nothing in flight, nothing parked: all packages done
+        if (__ballot(st != ST_DONE && st != ST_FLY) == 0) break;
 
         // ---- event batch
-        const int i = (int)(ps - sh);        // internal shell index
-        bool absorbing = false, scattering = false;
-        if (st == ST_EVT) {
-            if (ps == sentinel) {
-                // the flight left the cloud (the step into the sentinel is no crossing)
-                const double e = eps * (double)W;
-                if (src == 0) lc.esc0 += e; else lc.esc1 += e;
-                lc.escape++;
-                lc.cross--;
-                if (events == 0) lc.direct++;
-                st = ST_DEAD;
-            } else if (events >= o.max_events) {
-                lc.term += eps * (double)W;
-                lc.limit++;
-                st = ST_DEAD;
-            } else {
-                events++;
-                absorbing = ev_abs;
-                scattering = !ev_abs;
-            }
-        }
-
-        // refill lanes without a package from the wave-private pool, which takes
-        // `chunk` package indices from the global cursor at a time
-        bool launching = false;
-        const unsigned long long need = __ballot(st == ST_DEAD);
-        if (need) {
-            const unsigned long long cnt = __popcll(need);
-            const unsigned long long avail = pool_end - pool_next;
-            unsigned long long fresh = 0;
-            if (avail < cnt) {
-                const int leader = __ffsll((long long)need) - 1;
-                if (lane == leader) fresh = atomicAdd(cursor, chunk);
-                fresh = __shfl(fresh, leader, kWave);
-            }
-            if (st == ST_DEAD) {
-                const unsigned long long rank = __popcll(need & __lanemask_lt());
-                const unsigned long long gidx = rank < avail ? pool_next + rank : fresh + (rank - avail);
-                if (gidx >= total) {
-                    st = ST_DONE;
-                } else {
-                    src = gidx < mc.n_ext ? 0 : 1;
-                    const unsigned long long pid = (src ? mc.pid0[1] + (gidx - mc.n_ext) : mc.pid0[0] + gidx);
-                    eps = src ? mc.eps[1] : mc.eps[0];
-                    pid_lo = (uint32_t)pid;
-                    pid_hi = (uint32_t)(pid >> 32);
-                    blk = 0;
-                    events = 0;
-                    W = 1;
-                    launching = true;
-                }
-            }
-            if (avail < cnt) {
-                pool_next = fresh + (cnt - avail);
-                pool_end = fresh + chunk;
-            } else {
-                pool_next += cnt;
-            }
-        }
-        const bool ev = launching || absorbing || scattering;
-
-        // absorption: deposit E into the shell; A_before locates this package's
-        // slice [A_before, A_before + E] of the shell's absorbed power
-        const double E = absorbing ? eps * (double)W : 0.0;
-        double A_before = 0.0;
-        if (__ballot(absorbing)) A_before = fetch_add_energy<AGG>(mc.A, i - cav, E, absorbing);
-
-        Rand4 r1{0, 0, 0, 0}, r2b{0, 0, 0, 0};
-        if (ev) r1 = philox(blk++, pid_lo, pid_hi, (uint32_t)src, key0, key1);
-        if (absorbing) r2b = philox(blk++, pid_lo, pid_hi, (uint32_t)src, key0, key1);
-
-        // new frequency: source spectrum at launch, difference spectrum at re-emission
-        int row = 0;
-        if (absorbing) {
-            const double astar = (A_before + (((double)r1.x + 0.5) * 0x1p-32) * E) * mc.invM[i - cav];
-            row = count_le(G, n_t, (R)astar);
-            if (row > n_t - 1) { row = n_t - 1; lc.reabove++; }
-            lc.abs++;
-        }
-        if (launching || absorbing) {
-            const R *tab = launching ? cdf + src * K : D + (size_t)row * K;
-            k = min(count_le(tab, K, P<R>::uni(launching ? r1.x : r1.y)), K - 1);
-        }
-        const Dust d = dust[k];
-
-        // new direction: isotropic re-emission or Henyey-Greenstein scattering
-        if (absorbing || scattering) {
-            R r2 = b2 + t * t;
-            R rr = P<R>::sqrt_(r2);
-            R mun;
-            if (absorbing) {
-                mun = (R)2 * P<R>::uni(r1.z) - (R)1;
-                if (o.reemit_uniform) {
-                    const Shell s = *ps;
-                    const R rin = P<R>::sqrt_(s.r2_in);
-                    const R rout = P<R>::sqrt_(s.r2_out);
-                    const R c3 = rin * rin * rin + P<R>::uni(r2b.y) * (rout * rout * rout - rin * rin * rin);
-                    rr = P<R>::cbrt_(c3);
-                    r2 = rr * rr;
-                }
-            } else {
-                lc.scat++;
-                const R gg = d.g;
-                const R mu = rr > (R)0 ? t * P<R>::rcp(rr) : (R)1;
-                const R u0 = P<R>::uni(r1.x);
-                R ct;
-                if (gg > (R)-1e-6 && gg < (R)1e-6) {
-                    ct = (R)2 * u0 - (R)1;
-                } else {
-                    const R f = ((R)1 - gg * gg) * P<R>::rcp((R)1 - gg + (R)2 * gg * u0);
-                    ct = ((R)1 + gg * gg - f * f) * P<R>::rcp((R)2 * gg);
-                    ct = ct > (R)1 ? (R)1 : (ct < (R)-1 ? (R)-1 : ct);
-                }
-                const R st2 = ((R)1 - ct) * ((R)1 + ct);
-                const R sp2 = ((R)1 - mu) * ((R)1 + mu);
-                const R sn = P<R>::sqrt_((st2 > (R)0 ? st2 : (R)0) * (sp2 > (R)0 ? sp2 : (R)0));
-                mun = mu * ct + sn * P<R>::cos2pi(P<R>::uni(r1.y));
-                mun = mun > (R)1 ? (R)1 : (mun < (R)-1 ? (R)-1 : mun);
-            }
-            t = rr * mun;
-            b2 = r2 * ((R)1 - mun) * ((R)1 + mun);
-        }
-
-        // both free paths are redrawn after every event (Eq. 1)
-        R tauA = P<R>::nlog(P<R>::uni(absorbing ? r1.w : r1.z));
-        R tauS = P<R>::nlog(P<R>::uni(absorbing ? r2b.x : r1.w));
-
-        // launch geometry and launch weights (Eqs. 2-3, Eq. 5, Eqs. 9-12)
-        if (launching) {
-            lc.launch++;
-            if (src == 0) {
-                const R u1 = P<R>::uni(r1.y);
-                R mu;
-                if (o.k_bg == 0.5) {
-                    mu = P<R>::sqrt_(u1);
-                } else {
-                    const R kb = (R)o.k_bg;
-                    mu = P<R>::powr(u1, kb);
-                    W = (R)2 * kb * P<R>::powr(mu, (R)2 - (R)1 / kb);
-                }
-                ps = sentinel - 1;
-                t = -mu;
-                b2 = ((R)1 - mu) * ((R)1 + mu);
-            } else {
-                ps = sh;            // the centre (inside the cavity shell when there is one)
-                b2 = 0;
-                t = 0;
-            }
-            if (o.ffi) {
-                // extinction optical depth along the whole first ray
-                R tau0 = 0, tt = t;
-                for (const Shell *q = ps; q != sentinel;) {
-                    const Shell s = *q;
-                    const bool inward = (tt < (R)0) && (b2 < s.r2_in);
-                    const R arg = (inward ? s.r2_in : s.r2_out) - b2;
-                    const R sq = P<R>::sqrt_(arg > (R)0 ? arg : (R)0);
-                    const R tn = inward ? -sq : sq;
-                    const R lb = tn - tt > (R)0 ? tn - tt : (R)0;
-                    tau0 += d.kext * s.rho * lb;
-                    tt = tn;
-                    q += inward ? -1 : 1;
-                }
-                if (!(tau0 > (R)0)) {
-                    // no matter on the ray: the package leaves untouched
-                    if (src == 0) lc.esc0 += eps * (double)W; else lc.esc1 += eps * (double)W;
-                    lc.escape++;
-                    lc.direct++;
-                    launching = false;
-                    st = ST_DEAD;
-                } else {
-                    const R pf = -P<R>::expm1_(-tau0);
-                    lc.ffi += eps * (double)W * (double)(((R)1) - pf);
-                    W *= pf;
-                    const R tau = -P<R>::log1p_(-P<R>::uni(r1.z) * pf);
-                    if (P<R>::uni(r1.w) < d.alb) { tauS = tau * d.alb; tauA = P<R>::inf(); }
-                    else { tauA = tau * ((R)1 - d.alb); tauS = P<R>::inf(); }
-                }
-            }
-            W0 = W;
-        }
-
-        // weight floor (Sect. 2.2.1)
-        if ((absorbing || scattering) && W < (R)o.w_floor * W0) {
-            lc.term += eps * (double)W;
-            lc.floor++;
-            st = ST_DEAD;
-        } else if (launching || absorbing || scattering) {
-            const R sA = tauA * d.inv_kA;
-            const R sS = tauS * d.inv_kS;
-            ev_abs = sA <= sS;
-            sig = ev_abs ? sA : sS;
-            st = ST_FLY;
-        }
+        event_pass();
+        cur = P<R>::shell(ps);
     }
-
 }
 
 // Sum the per-lane counters over the wave and add them to the launch statistics.
@@ -532,7 +586,7 @@ __device__ __forceinline__ void single_model(const TraceParams &p, const typenam
 template <bool AGG>
 __global__ __launch_bounds__(kBlockFP32) void ire_trace_f32(TraceParams p) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int nsh = p.n + p.cavity + 1, K = p.K, n_t = p.n_t;
+    const int nsh = p.n + p.cavity + kSentinels, K = p.K, n_t = p.n_t;
     ShellF *s_sh = reinterpret_cast<ShellF *>(smem);
     DustF *s_dust = reinterpret_cast<DustF *>(s_sh + nsh);
     float *s_cdf = reinterpret_cast<float *>(s_dust + K);
@@ -551,7 +605,7 @@ __global__ __launch_bounds__(kBlockFP32) void ire_trace_f32(TraceParams p) {
     const long long gtid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     LaneCounters lc;
     trace_model<float, AGG>(mc, o, s_dust, s_cdf, s_G, s_D, K, n_t, &p.stats->cursor, p.chunk,
-                            p.max_lanes > 0 && gtid >= p.max_lanes, lc);
+                                   p.max_lanes > 0 && gtid >= p.max_lanes, lc);
     flush_counters(lc, p.stats);
 }
 
@@ -563,7 +617,7 @@ __global__ __launch_bounds__(256) void ire_trace_f64(TraceParams p) {
     const long long gtid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     LaneCounters lc;
     trace_model<double, AGG>(mc, o, p.dustd, p.cdfd, p.Gd, p.Dd, p.K, p.n_t, &p.stats->cursor, p.chunk,
-                             p.max_lanes > 0 && gtid >= p.max_lanes, lc);
+                                p.max_lanes > 0 && gtid >= p.max_lanes, lc);
     flush_counters(lc, p.stats);
 }
 
@@ -649,7 +703,7 @@ __global__ __launch_bounds__(kBlockFP32) void ire_trace_batch(BatchParams p) {
         if (it >= (unsigned long long)p.n_items) break;
         const BatchItemDev item = p.items[it];
         const BatchModelDev bm = p.models[item.model];
-        const int nt = bm.n + bm.cav + 1;
+        const int nt = bm.n + bm.cav + kSentinels;
         for (int j = threadIdx.x; j < nt; j += blockDim.x) s_sh[j] = p.shells[bm.shell_off + j];
         __syncthreads();
         ModelCtx<float> mc;
@@ -710,23 +764,31 @@ size_t trace_lds_bytes(int n_table, int K, int n_t) {
            (size_t)n_t * sizeof(float) + (size_t)n_t * K * sizeof(float);
 }
 
-hipError_t trace_configure(int fp64, int aggregate, size_t lds) {
-    if (fp64) return hipSuccess;
-    const void *f = aggregate ? reinterpret_cast<const void *>(&ire_trace_f32<true>)
-                              : reinterpret_cast<const void *>(&ire_trace_f32<false>);
-    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+static const void *f32_kernel(int aggregate) {
+    return aggregate ? reinterpret_cast<const void *>(&ire_trace_f32<true>)
+                     : reinterpret_cast<const void *>(&ire_trace_f32<false>);
 }
 
-hipError_t launch_trace(const TraceParams &p, int fp64, int aggregate, int grid, int block,
-                        size_t lds, hipStream_t s) {
+static const void *batch_kernel(int aggregate) {
+    return aggregate ? reinterpret_cast<const void *>(&ire_trace_batch<true>)
+                     : reinterpret_cast<const void *>(&ire_trace_batch<false>);
+}
+
+hipError_t trace_configure(int fp64, int aggregate, size_t lds) {
+    if (fp64) return hipSuccess;
+    return hipFuncSetAttribute(f32_kernel(aggregate), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+hipError_t launch_trace(const TraceParams &p, int fp64, int aggregate, int grid, int block, size_t lds,
+                        hipStream_t s) {
     if (fp64) {
         if (aggregate) hipLaunchKernelGGL(ire_trace_f64<true>, dim3(grid), dim3(block), 0, s, p);
         else hipLaunchKernelGGL(ire_trace_f64<false>, dim3(grid), dim3(block), 0, s, p);
-    } else {
-        if (aggregate) hipLaunchKernelGGL(ire_trace_f32<true>, dim3(grid), dim3(block), lds, s, p);
-        else hipLaunchKernelGGL(ire_trace_f32<false>, dim3(grid), dim3(block), lds, s, p);
+        return hipGetLastError();
     }
-    return hipGetLastError();
+    TraceParams q = p;
+    void *args[] = {&q};
+    return hipLaunchKernel(f32_kernel(aggregate), dim3(grid), dim3(block), args, lds, s);
 }
 
 hipError_t launch_zero(double *A, int n, DevStats *st, int clear_counts, hipStream_t s) {
@@ -751,15 +813,13 @@ hipError_t launch_finalize(const FinalizeParams &p, hipStream_t s) {
 int trace_block_fp32() { return kBlockFP32; }
 
 hipError_t batch_configure(int aggregate, size_t lds) {
-    const void *f = aggregate ? reinterpret_cast<const void *>(&ire_trace_batch<true>)
-                              : reinterpret_cast<const void *>(&ire_trace_batch<false>);
-    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    return hipFuncSetAttribute(batch_kernel(aggregate), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 hipError_t launch_trace_batch(const BatchParams &p, int aggregate, int grid, size_t lds, hipStream_t s) {
-    if (aggregate) hipLaunchKernelGGL(ire_trace_batch<true>, dim3(grid), dim3(kBlockFP32), lds, s, p);
-    else hipLaunchKernelGGL(ire_trace_batch<false>, dim3(grid), dim3(kBlockFP32), lds, s, p);
-    return hipGetLastError();
+    BatchParams q = p;
+    void *args[] = {&q};
+    return hipLaunchKernel(batch_kernel(aggregate), dim3(grid), dim3(kBlockFP32), args, lds, s);
 }
 
 hipError_t launch_zero_batch(double *A, size_t n_shells, DevStats *st, hipStream_t s) {

@@ -414,6 +414,74 @@ int sur_predict(sur_net *s, const float *X, int64_t n, float *mean_logT, float *
     return rc;
 }
 
+int sur_predict_models_dev(sur_net *s, int64_t n_models, int64_t n_rows, const float *model_x_dev,
+                           const int64_t *row_off_dev, const int64_t *radius_off_dev, const float *radius_dev,
+                           int64_t n_radius, float *mean_dev, float *spread_dev, float *model_spread_dev,
+                           void *hip_stream) {
+    if (!s) return IRE_E_INVALID;
+    if (n_models < 0 || n_rows < 0 || n_radius < 0) return s->fail(IRE_E_INVALID, "negative size");
+    if (n_models == 0) return IRE_OK;
+    if (!model_x_dev || !row_off_dev || !radius_off_dev || (!radius_dev && n_radius > 0) ||
+        (n_rows > 0 && (!mean_dev || !spread_dev)))
+        return s->fail(IRE_E_INVALID, "null pointer");
+    hipError_t e;
+    if ((e = hipSetDevice(s->device)) != hipSuccess) return s->hip_fail(e, "hipSetDevice");
+    const sur::ModelRows q{n_models, n_radius, model_x_dev, row_off_dev, radius_off_dev, radius_dev};
+    if ((e = sur::launch_predict_models(s->view(), q, n_rows, mean_dev, spread_dev, model_spread_dev,
+                                        reinterpret_cast<hipStream_t>(hip_stream))) != hipSuccess)
+        return s->hip_fail(e, "predict models");
+    return IRE_OK;
+}
+
+int sur_predict_models(sur_net *s, int64_t n_models, const float *model_x, const int64_t *row_off,
+                       const int64_t *radius_off, const float *radius, int64_t n_radius, float *mean_logT,
+                       float *spread, float *model_spread) {
+    if (!s) return IRE_E_INVALID;
+    if (n_models < 0 || n_radius < 0) return s->fail(IRE_E_INVALID, "negative size");
+    if (n_models == 0) return IRE_OK;
+    if (!model_x || !row_off || !radius_off || (!radius && n_radius > 0)) return s->fail(IRE_E_INVALID, "null pointer");
+    if (row_off[0] != 0) return s->fail(IRE_E_INVALID, "row_off[0] must be 0");
+    for (int64_t m = 0; m < n_models; ++m) {
+        const int64_t nm = row_off[m + 1] - row_off[m];
+        if (nm < 0) return s->fail(IRE_E_INVALID, "row offsets must not decrease");
+        if (nm > 0 && (radius_off[m] < 0 || radius_off[m] + nm > n_radius))
+            return s->fail(IRE_E_INVALID, "radius range of a model outside the radius table");
+    }
+    for (int64_t j = 0; j < n_models * (sur::kFeatures - 1); ++j)
+        if (!std::isfinite(model_x[j])) return s->fail(IRE_E_INVALID, "non-finite model parameter");
+    for (int64_t j = 0; j < n_radius; ++j)
+        if (!std::isfinite(radius[j])) return s->fail(IRE_E_INVALID, "non-finite radius");
+    const int64_t n_rows = row_off[n_models];
+    if (n_rows > 0 && (!mean_logT || !spread)) return s->fail(IRE_E_INVALID, "null output");
+    hipError_t e;
+    if ((e = hipSetDevice(s->device)) != hipSuccess) return s->hip_fail(e, "hipSetDevice");
+    DevBuf<float> dx, dr, dm, ds, dms;
+    DevBuf<int64_t> dro, dra;
+    int rc = IRE_OK;
+    if ((e = dx.ensure((size_t)n_models * (sur::kFeatures - 1))) != hipSuccess ||
+        (e = dr.ensure((size_t)n_radius)) != hipSuccess || (e = dm.ensure((size_t)n_rows)) != hipSuccess ||
+        (e = ds.ensure((size_t)n_rows)) != hipSuccess || (e = dms.ensure((size_t)n_models)) != hipSuccess ||
+        (e = dro.ensure((size_t)n_models + 1)) != hipSuccess || (e = dra.ensure((size_t)n_models)) != hipSuccess) {
+        rc = s->fail(IRE_E_NOMEM, "prediction buffers");
+    } else if ((e = hipMemcpy(dx.p, model_x, (size_t)n_models * (sur::kFeatures - 1) * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess ||
+               (n_radius > 0 && (e = hipMemcpy(dr.p, radius, (size_t)n_radius * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) ||
+               (e = hipMemcpy(dro.p, row_off, ((size_t)n_models + 1) * sizeof(int64_t), hipMemcpyHostToDevice)) != hipSuccess ||
+               (e = hipMemcpy(dra.p, radius_off, (size_t)n_models * sizeof(int64_t), hipMemcpyHostToDevice)) != hipSuccess) {
+        rc = s->hip_fail(e, "upload");
+    } else {
+        const sur::ModelRows q{n_models, n_radius, dx.p, dro.p, dra.p, dr.p};
+        if ((e = sur::launch_predict_models(s->view(), q, n_rows, dm.p, ds.p, dms.p, nullptr)) != hipSuccess ||
+            (e = hipDeviceSynchronize()) != hipSuccess)
+            rc = s->hip_fail(e, "predict models");
+        else if ((n_rows > 0 && ((e = hipMemcpy(mean_logT, dm.p, (size_t)n_rows * sizeof(float), hipMemcpyDeviceToHost)) != hipSuccess ||
+                                 (e = hipMemcpy(spread, ds.p, (size_t)n_rows * sizeof(float), hipMemcpyDeviceToHost)) != hipSuccess)) ||
+                 (model_spread && (e = hipMemcpy(model_spread, dms.p, (size_t)n_models * sizeof(float), hipMemcpyDeviceToHost)) != hipSuccess))
+            rc = s->hip_fail(e, "download");
+    }
+    dx.release(); dr.release(); dm.release(); ds.release(); dms.release(); dro.release(); dra.release();
+    return rc;
+}
+
 int sur_save(sur_net *s, const char *path) {
     if (!s || !path) return IRE_E_INVALID;
     std::vector<float> p((size_t)s->members * s->p_stride);

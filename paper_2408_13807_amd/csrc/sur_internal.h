@@ -27,6 +27,17 @@ struct NetView {
     float y_mean, y_std, y_inv_std;
 };
 
+// Whole-model prediction inputs (device pointers): model m owns output rows
+// [row_off[m], row_off[m+1]); its cloud parameters (feature columns 0..4) are
+// model_x[m*5 .. m*5+4]; the shells' relative mid-radii (column 5) are
+// radius[radius_off[m] + j], j < row_off[m+1] - row_off[m].
+struct ModelRows {
+    int64_t n_models, n_radius;
+    const float *model_x;
+    const int64_t *row_off, *radius_off;
+    const float *radius;
+};
+
 struct TrainView {
     int64_t batch;              // rows per member and step
     float *xb, *yb;             // [M][batch][kFeatures], [M][batch] gathered mini-batch
@@ -66,6 +77,8 @@ __device__ __forceinline__ void scatter_param(const NetView &v, int m, size_t q,
 size_t predict_lds();
 hipError_t configure();
 hipError_t launch_predict(const NetView &v, const float *X, int64_t n, float *mean_logT, float *spread, hipStream_t s);
+hipError_t launch_predict_models(const NetView &v, const ModelRows &q, int64_t n_rows, float *mean_logT,
+                                 float *spread, float *model_spread, hipStream_t s);
 // One training step on the batch in t (gathered from X, y when X is not null);
 // with `update`, an Adam step and the step counter increment follow.
 hipError_t launch_train_step(const NetView &v, const TrainView &t, const float *X, const float *y, int64_t n_data,

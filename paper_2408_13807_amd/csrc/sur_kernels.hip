@@ -40,13 +40,22 @@ __device__ __forceinline__ f32x16 mfma(const bf16x8 &a, const bf16x8 &b, const f
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
+// The network sees one input derived from the six: log10 of the relative
+// radius (floored at 1e-4) shifted by 1.5, which spreads the inner shells of
+// log-spaced grids that r / R_out alone packs near zero.
+constexpr int kLogRadius = kFeatures;
+__device__ __forceinline__ float log_radius_input(float r) { return log10f(fmaxf(r, 1e-4f)) + 1.5f; }
+
 // Normalised inputs of rows [row0, row0 + kR) into the LDS input tile (zero padded).
 __device__ __forceinline__ void load_inputs(const float *X, int64_t n, int64_t row0, const NetView &v, __bf16 *xs) {
     for (int j = threadIdx.x; j < kR * kIn; j += blockDim.x) {
         const int r = j / kIn, c = j % kIn;
         const int64_t row = row0 + r;
         float x = 0.0f;
-        if (c < kFeatures && row < n) x = (X[row * kFeatures + c] - v.x_mean[c]) * v.x_inv_std[c];
+        if (row < n) {
+            if (c < kFeatures) x = (X[row * kFeatures + c] - v.x_mean[c]) * v.x_inv_std[c];
+            else if (c == kLogRadius) x = log_radius_input(X[row * kFeatures + kFeatures - 1]);
+        }
         xs[r * kLdX + c] = (__bf16)x;
     }
 }
@@ -115,14 +124,69 @@ __device__ __forceinline__ float out_row(const __bf16 *h, const float *wout, flo
 // ---------------------------------------------------------------------------
 // Inference: every member on every row; mean log10 T and relative spread of T.
 
-__global__ __launch_bounds__(kThreads) void sur_predict_kernel(NetView v, const float *X, int64_t n, float *mean_logT,
+// Row inputs for prediction: a row-major [n][kFeatures] matrix ...
+struct RowInputs {
+    const float *X;
+    __device__ __forceinline__ void operator()(int64_t n, int64_t row0, const NetView &v, __bf16 *xs) const {
+        load_inputs(X, n, row0, v, xs);
+    }
+};
+
+// ... or whole models: the cloud parameters once per model (feature columns
+// 0..4) and the shells' relative mid-radii (column 5) from a radius table in
+// which models with the same shell grid may share their values.
+struct ModelInputs {
+    ModelRows q;
+    __device__ __forceinline__ void operator()(int64_t n, int64_t row0, const NetView &v, __bf16 *xs) const {
+        __shared__ int64_t s_model[kR];
+        __shared__ int64_t s_first;
+        if (threadIdx.x == 0) {
+            // the model holding row0: last m with row_off[m] <= row0
+            int64_t lo = 0, hi = q.n_models - 1;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi + 1) >> 1;
+                if (q.row_off[mid] <= row0) lo = mid; else hi = mid - 1;
+            }
+            s_first = lo;
+        }
+        __syncthreads();
+        if (threadIdx.x < kR) {
+            const int64_t row = row0 + threadIdx.x;
+            int64_t m = s_first;
+            if (row < n)
+                while (m + 1 < q.n_models && q.row_off[m + 1] <= row) ++m;
+            s_model[threadIdx.x] = m;
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < kR * kIn; j += blockDim.x) {
+            const int r = j / kIn, c = j % kIn;
+            const int64_t row = row0 + r;
+            float x = 0.0f;
+            if ((c < kFeatures || c == kLogRadius) && row < n) {
+                const int64_t m = s_model[r];
+                if (c < kFeatures - 1) {
+                    x = (q.model_x[m * (kFeatures - 1) + c] - v.x_mean[c]) * v.x_inv_std[c];
+                } else {
+                    const int64_t k = q.radius_off[m] + (row - q.row_off[m]);
+                    const float rr = (k >= 0 && k < q.n_radius) ? q.radius[k] : 0.0f;
+                    x = c == kLogRadius ? log_radius_input(rr)
+                                        : (rr - v.x_mean[kFeatures - 1]) * v.x_inv_std[kFeatures - 1];
+                }
+            }
+            xs[r * kLdX + c] = (__bf16)x;
+        }
+    }
+};
+
+template <typename Inputs>
+__global__ __launch_bounds__(kThreads) void sur_predict_kernel(NetView v, Inputs in, int64_t n, float *mean_logT,
                                                                float *spread) {
     extern __shared__ __align__(16) unsigned char smem[];
     __bf16 *xs = reinterpret_cast<__bf16 *>(smem);
     __bf16 *h0 = xs + kR * kLdX;
     __bf16 *h1 = h0 + kR * kLd;
     const int64_t row0 = (int64_t)blockIdx.x * kR;
-    load_inputs(X, n, row0, v, xs);
+    in(n, row0, v, xs);
     float s_log = 0.0f, s_T = 0.0f, s_T2 = 0.0f;
     for (int m = 0; m < v.members; ++m) {
         const __bf16 *W = v.W + (size_t)m * v.w_stride;
@@ -154,6 +218,20 @@ __global__ __launch_bounds__(kThreads) void sur_predict_kernel(NetView v, const 
             spread[row] = sqrtf(var) / mT;
         }
     }
+}
+
+// Largest row spread of every model (one wave per model).
+__global__ __launch_bounds__(256) void sur_model_max(const float *spread, int64_t n_rows, ModelRows q,
+                                                     float *model_spread) {
+    const int lane = threadIdx.x & 63;
+    const int64_t m = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (m >= q.n_models) return;
+    const int64_t a = q.row_off[m] > 0 ? q.row_off[m] : 0;
+    const int64_t b = q.row_off[m + 1] < n_rows ? q.row_off[m + 1] : n_rows;
+    float mx = 0.0f;
+    for (int64_t r = a + lane; r < b; r += 64) mx = fmaxf(mx, spread[r]);
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+    if (lane == 0) model_spread[m] = mx;
 }
 
 // ---------------------------------------------------------------------------
@@ -438,7 +516,10 @@ size_t wgrad_lds() { return (size_t)(kW + 128) * (kR + 8) * 2; }
 
 hipError_t configure() {
     hipError_t e;
-    if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(&sur_predict_kernel),
+    if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(&sur_predict_kernel<RowInputs>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)predict_lds())) != hipSuccess)
+        return e;
+    if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(&sur_predict_kernel<ModelInputs>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)predict_lds())) != hipSuccess)
         return e;
     if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(&sur_train_fwd),
@@ -453,8 +534,21 @@ hipError_t configure() {
 
 hipError_t launch_predict(const NetView &v, const float *X, int64_t n, float *mean_logT, float *spread, hipStream_t s) {
     const int64_t blocks = (n + kR - 1) / kR;
-    hipLaunchKernelGGL(sur_predict_kernel, dim3((unsigned)blocks), dim3(kThreads), predict_lds(), s, v, X, n,
-                       mean_logT, spread);
+    hipLaunchKernelGGL(sur_predict_kernel<RowInputs>, dim3((unsigned)blocks), dim3(kThreads), predict_lds(), s, v,
+                       RowInputs{X}, n, mean_logT, spread);
+    return hipGetLastError();
+}
+
+hipError_t launch_predict_models(const NetView &v, const ModelRows &q, int64_t n_rows, float *mean_logT,
+                                 float *spread, float *model_spread, hipStream_t s) {
+    if (n_rows > 0) {
+        const int64_t blocks = (n_rows + kR - 1) / kR;
+        hipLaunchKernelGGL(sur_predict_kernel<ModelInputs>, dim3((unsigned)blocks), dim3(kThreads), predict_lds(), s,
+                           v, ModelInputs{q}, n_rows, mean_logT, spread);
+    }
+    if (model_spread && q.n_models > 0)
+        hipLaunchKernelGGL(sur_model_max, dim3((unsigned)((q.n_models + 3) / 4)), dim3(256), 0, s, spread, n_rows, q,
+                           model_spread);
     return hipGetLastError();
 }
 

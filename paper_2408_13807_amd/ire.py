@@ -54,6 +54,12 @@ class ModelDesc(ct.Structure):
                 ("n_packages", ct.c_uint64), ("seed", ct.c_uint64)]
 
 
+_MODEL_DESC_DTYPE = np.dtype({"names": ["n_shells", "source", "scale", "n_packages", "seed"],
+                              "formats": [np.int32, np.int32, np.float64, np.uint64, np.uint64],
+                              "offsets": [getattr(ModelDesc, f).offset for f, _ in ModelDesc._fields_],
+                              "itemsize": ct.sizeof(ModelDesc)})
+
+
 class BatchOptions(ct.Structure):
     _fields_ = [("k_bg", ct.c_double), ("ffi", ct.c_int32), ("w_floor", ct.c_double),
                 ("max_events", ct.c_uint64), ("reemit_uniform", ct.c_int32), ("aggregate", ct.c_int32),
@@ -327,10 +333,13 @@ class IREBatch:
 
     def set_models(self, n_shells, source, scale, n_packages, seeds, r_edges_flat, rho_flat):
         M = len(n_shells)
-        descs = (ModelDesc * M)()
-        for m in range(M):
-            descs[m] = ModelDesc(int(n_shells[m]), int(source[m]), float(scale[m]), int(n_packages[m]),
-                                 int(seeds[m]))
+        rec = np.zeros(M, dtype=_MODEL_DESC_DTYPE)
+        rec["n_shells"] = n_shells
+        rec["source"] = source
+        rec["scale"] = scale
+        rec["n_packages"] = n_packages
+        rec["seed"] = seeds
+        descs = rec.ctypes.data_as(ct.POINTER(ModelDesc))
         r, pr = _arr(r_edges_flat)
         d, pd = _arr(rho_flat)
         self._check(_lib.ire_batch_set_models(self._h, M, descs, pr, pd))
@@ -368,16 +377,13 @@ def batch_from_workloads(params: dict, models: list[int] | None = None, device: 
     b.set_dust(d["nu"], d["kabs"], d["albedo"], d["g"])
     b.set_temperature_grid(3.0, 1600.0, 512)
     b.set_sources(wl.isrf(d["nu"]), wl.blackbody(d["nu"], 5000.0))
-    r_all, rho_all, n_sh, src, scale, npk, seeds = [], [], [], [], [], [], []
-    for m in idx:
-        mm = wl.batch_model(params, m)
-        r_all.append(mm["r_edges"])
-        rho_all.append(mm["rho"])
-        n_sh.append(len(mm["rho"]))
-        central = int(params["central"][m])
-        src.append(IRE_SRC_POINT if central else IRE_SRC_EXTERNAL)
-        scale.append(float(params["L"][m]) if central else float(params["field_scale"][m]))
-        npk.append(max(1, int(round(int(params["n_pkg"][m]) * package_scale))))
-        seeds.append(int(params["seed"][m]))
-    b.set_models(n_sh, src, scale, npk, seeds, np.concatenate(r_all), np.concatenate(rho_all))
+    idx = np.asarray(idx, np.int64)
+    r_flat, rho_flat = wl.study_shells(params, idx)
+    central = params["central"][idx] == 1
+    n_sh = params["n"][idx].astype(np.int64)
+    src = np.where(central, IRE_SRC_POINT, IRE_SRC_EXTERNAL)
+    scale = np.where(central, params["L"][idx], params["field_scale"][idx])
+    npk = np.maximum(1, np.round(params["n_pkg"][idx] * package_scale)).astype(np.int64)
+    seeds = params["seed"][idx]
+    b.set_models(n_sh, src, scale, npk, seeds, r_flat, rho_flat)
     return b

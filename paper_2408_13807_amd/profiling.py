@@ -9,6 +9,9 @@
         dispatches: the VALU instructions one lane executes per event type
     python -m paper_2408_13807_amd.profiling summary DB [DB ...]
         markdown summary of rocprofv3 databases (kernel statistics and counters)
+    python -m paper_2408_13807_amd.profiling copy [MiB]
+        one device-to-device copy of MiB (default 1024) MiB: the reference
+        dispatch that scales FETCH_SIZE / WRITE_SIZE into bytes
 """
 from __future__ import annotations
 
@@ -85,7 +88,7 @@ def summary(dbs: list[str]) -> str:
             lines.append("| dispatch kernel | " + " | ".join(keys) + " |")
             lines.append("|---|" + "---|" * len(keys))
             for c in cnt:
-                if "ire_" not in c["kernel"]:
+                if not any(k in c["kernel"] for k in ("ire_", "sur_", "copy", "Copy")):
                     continue
                 lines.append(f"| `{c['kernel'][:60]}` | " + " | ".join(f"{c.get(k, float('nan')):.6g}" for k in keys) + " |")
             lines.append("")
@@ -108,6 +111,15 @@ def main(argv: list[str]) -> int:
         print(json.dumps(valu_fit(argv[1], cases), indent=1))
     elif cmd == "summary":
         print(summary(argv[1:]))
+    elif cmd == "copy":
+        import torch
+        n = (int(argv[1]) if len(argv) > 1 else 1024) << 18   # float32 elements
+        x = torch.ones(n, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}))
     else:
         print(__doc__)
         return 1

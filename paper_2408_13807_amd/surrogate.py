@@ -27,7 +27,7 @@ class TrainOpts(ct.Structure):
 
 EXPORTS = ("sur_default_train_opts", "sur_create", "sur_destroy", "sur_set_normalization", "sur_param_count",
            "sur_get_params", "sur_set_params", "sur_train", "sur_gradients", "sur_predict", "sur_predict_dev",
-           "sur_save", "sur_load", "sur_last_error")
+           "sur_predict_models", "sur_predict_models_dev", "sur_save", "sur_load", "sur_last_error")
 
 _lib.sur_default_train_opts.argtypes = [ct.POINTER(TrainOpts)]
 _lib.sur_create.argtypes = [ct.c_int, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_uint64, ct.POINTER(_H)]
@@ -42,6 +42,10 @@ _lib.sur_train.argtypes = [_H, _FP, _FP, ct.c_int64, ct.POINTER(TrainOpts), ct.c
 _lib.sur_gradients.argtypes = [_H, _FP, _FP, ct.c_int64, _FP, _FP]
 _lib.sur_predict.argtypes = [_H, _FP, ct.c_int64, _FP, _FP]
 _lib.sur_predict_dev.argtypes = [_H, ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_void_p]
+_I64P = ct.POINTER(ct.c_int64)
+_lib.sur_predict_models.argtypes = [_H, ct.c_int64, _FP, _I64P, _I64P, _FP, ct.c_int64, _FP, _FP, _FP]
+_lib.sur_predict_models_dev.argtypes = [_H, ct.c_int64, ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                        ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p]
 _lib.sur_save.argtypes = [_H, ct.c_char_p]
 _lib.sur_load.argtypes = [_H, ct.c_char_p]
 _lib.sur_last_error.argtypes = [_H]
@@ -74,7 +78,7 @@ class SurNet:
         self.n_params = int(_lib.sur_param_count(h))
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.sur_destroy(self._h)
             self._h = None
 
@@ -126,6 +130,29 @@ class SurNet:
     def predict_dev(self, X_ptr: int, n: int, mean_ptr: int, spread_ptr: int, stream=None):
         self._check(_lib.sur_predict_dev(self._h, X_ptr, int(n), mean_ptr, spread_ptr, _ire._stream_ptr(stream)))
 
+    def predict_models(self, model_x, row_off, radius_off, radius):
+        """Whole-model prediction (sur_predict_models): per-row mean log10 T and
+        spread, and the largest spread of every model."""
+        x, px = _f32(model_x)
+        ro = np.ascontiguousarray(row_off, dtype=np.int64)
+        ra = np.ascontiguousarray(radius_off, dtype=np.int64)
+        r, pr = _f32(radius)
+        n_models, n_rows = len(ra), int(ro[-1])
+        mean = np.zeros(n_rows, np.float32)
+        spread = np.zeros(n_rows, np.float32)
+        mspread = np.zeros(n_models, np.float32)
+        self._check(_lib.sur_predict_models(self._h, n_models, px, ro.ctypes.data_as(_I64P), ra.ctypes.data_as(_I64P),
+                                            pr, len(r), mean.ctypes.data_as(_FP), spread.ctypes.data_as(_FP),
+                                            mspread.ctypes.data_as(_FP)))
+        return mean, spread, mspread
+
+    def predict_models_dev(self, n_models: int, n_rows: int, model_x_ptr: int, row_off_ptr: int, radius_off_ptr: int,
+                           radius_ptr: int, n_radius: int, mean_ptr: int, spread_ptr: int, model_spread_ptr: int,
+                           stream=None):
+        self._check(_lib.sur_predict_models_dev(self._h, int(n_models), int(n_rows), model_x_ptr, row_off_ptr,
+                                                radius_off_ptr, radius_ptr, int(n_radius), mean_ptr, spread_ptr,
+                                                model_spread_ptr, _ire._stream_ptr(stream)))
+
     def save(self, path: str):
         self._check(_lib.sur_save(self._h, path.encode()))
 
@@ -137,30 +164,55 @@ class SurNet:
 # Parameter-study pipeline
 
 
-def model_rows(params: dict, models) -> tuple[np.ndarray, np.ndarray]:
-    """Surrogate inputs of every shell of the given models, and the row offsets per model."""
-    feats, offs = [], [0]
-    for m in models:
-        mm = wl.batch_model(params, int(m))
-        f = wl.surrogate_features(params, int(m), mm["r_edges"])
-        feats.append(f)
-        offs.append(offs[-1] + len(f))
-    return np.concatenate(feats), np.asarray(offs, np.int64)
+def ire_profiles(params: dict, models, package_scale: float = 1.0, chunk: int = 16384, device: int = 0,
+                 options: dict | None = None) -> dict:
+    """Per-shell temperatures of study models from batched IRE launches of at
+    most `chunk` models each; T of all models end to end with row offsets."""
+    models = np.asarray(models, np.int64)
+    T, A, secs, pk = [], [], 0.0, 0
+    for c0 in range(0, len(models), chunk):
+        b = _ire.batch_from_workloads(params, models[c0:c0 + chunk], device=device, package_scale=package_scale)
+        if options:
+            b.set_options(**options)
+        t0 = time.perf_counter()
+        b.run()
+        r = b.results(allow_limit=True)
+        secs += time.perf_counter() - t0
+        pk += int(r["stats"]["n_launch"])
+        T.append(r["T"])
+        A.append(r["A"])
+        b.close()
+    n = params["n"][models].astype(np.int64)
+    row_off = np.zeros(len(models) + 1, np.int64)
+    np.cumsum(n, out=row_off[1:])
+    return dict(T=np.concatenate(T) if T else np.zeros(0), A=np.concatenate(A) if A else np.zeros(0),
+                row_off=row_off, seconds=secs, packages=pk)
 
 
-def ire_temperatures(params: dict, models, package_scale: float = 1.0, device: int = 0, autotune: bool = False):
-    """Per-shell temperatures of the models from one batched IRE launch."""
-    b = _ire.batch_from_workloads(params, models, device=device, package_scale=package_scale)
-    if autotune:
-        b.autotune(fraction=0.05)
-    t0 = time.perf_counter()
-    b.run()
-    r = b.results(allow_limit=True)
-    dt = time.perf_counter() - t0
-    T = r["T"].copy()
-    offs = b.offsets.copy()
-    b.close()
-    return T, offs, dt, r["stats"]
+def training_set(params: dict, models, T: np.ndarray, t_floor: float = 3.0) -> tuple[np.ndarray, np.ndarray]:
+    """Rows (features, log10 T) of the models for training; shells left at the
+    temperature floor (no absorbed energy in the run) carry no information and
+    are dropped."""
+    X, _ = wl.study_features(params, models)
+    keep = T > t_floor * (1 + 1e-6)
+    return X[keep], np.log10(T[keep]).astype(np.float32)
+
+
+def fit(X: np.ndarray, y: np.ndarray, members: int = 5, depth: int = 4, steps: int = 20000, batch: int = 4096,
+        lr: float = 2e-3, lr_min: float = 2e-5, seed: int = 1, device: int = 0) -> SurNet:
+    """Train an ensemble on (X, y) with inputs and target standardised."""
+    net = SurNet(members=members, depth=depth, seed=seed, device=device)
+    xs = X.std(axis=0)
+    net.set_normalization(X.mean(axis=0), np.where(xs > 0, xs, 1.0), float(y.mean()), float(max(y.std(), 1e-6)))
+    net.last_loss = net.train(X, y, steps=steps, batch=batch, lr=lr, lr_min=lr_min, seed=seed)
+    return net
+
+
+def predict_models(net: SurNet, params: dict, models) -> dict:
+    """Surrogate temperatures of whole models (host arrays)."""
+    q = wl.study_model_inputs(params, models)
+    mean, spread, mspread = net.predict_models(q["model_x"], q["row_off"], q["radius_off"], q["radius"])
+    return dict(logT=mean, spread=spread, model_spread=mspread, row_off=q["row_off"])
 
 
 def predict_with_fallback(net: SurNet, params: dict, models, threshold: float = 0.02, package_scale: float = 1.0,
@@ -168,21 +220,29 @@ def predict_with_fallback(net: SurNet, params: dict, models, threshold: float = 
     """Surrogate temperatures for every shell of the models; every model with a
     shell whose ensemble spread std(T)/mean(T) exceeds `threshold` is re-run with
     the batched IRE tracer and takes the tracer's temperatures."""
+    models = np.asarray(models, np.int64)
     t0 = time.perf_counter()
-    X, offs = model_rows(params, models)
+    p = predict_models(net, params, models)
     t1 = time.perf_counter()
-    mean_logT, spread = net.predict(X)
-    t2 = time.perf_counter()
-    T = 10.0 ** mean_logT.astype(np.float64)
-    per_model = np.maximum.reduceat(spread, offs[:-1]) if len(models) else np.zeros(0)
-    flagged = [m for m, s in zip(models, per_model) if s > threshold]
+    T = 10.0 ** p["logT"].astype(np.float64)
+    offs = p["row_off"]
+    flagged = np.nonzero(p["model_spread"] > threshold)[0]
     ire_s = 0.0
-    if flagged:
-        Tf, offf, ire_s, _ = ire_temperatures(params, flagged, package_scale=package_scale, device=device)
-        pos = {m: j for j, m in enumerate(models)}
-        for j, m in enumerate(flagged):
-            k = pos[m]
-            T[offs[k]:offs[k + 1]] = Tf[offf[j]:offf[j + 1]]
-    t3 = time.perf_counter()
-    return dict(T=T, offsets=offs, spread=spread, flagged=flagged, seconds_features=t1 - t0,
-                seconds_predict=t2 - t1, seconds_fallback=ire_s, seconds_total=t3 - t0)
+    if len(flagged):
+        r = ire_profiles(params, models[flagged], package_scale=package_scale, device=device)
+        ire_s = r["seconds"]
+        for j, k in enumerate(flagged):
+            T[offs[k]:offs[k + 1]] = r["T"][r["row_off"][j]:r["row_off"][j + 1]]
+    t2 = time.perf_counter()
+    return dict(T=T, row_off=offs, spread=p["spread"], model_spread=p["model_spread"], flagged=flagged,
+                seconds_predict=t1 - t0, seconds_fallback=ire_s, seconds_total=t2 - t0)
+
+
+def model_errors(T: np.ndarray, T_ref: np.ndarray, row_off: np.ndarray) -> np.ndarray:
+    """Mean relative temperature error |T - T_ref| / T_ref over the shells of each model."""
+    d = np.abs(T - T_ref) / T_ref
+    n = np.diff(row_off)
+    out = np.zeros(len(n))
+    nz = n > 0
+    out[nz] = np.add.reduceat(d, row_off[:-1][nz]) / n[nz]
+    return out

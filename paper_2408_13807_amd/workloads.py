@@ -184,3 +184,80 @@ def surrogate_features(params: dict, m: int, r_edges: np.ndarray) -> np.ndarray:
     f[:, 4] = central
     f[:, 5] = rm
     return f
+
+
+def radius_table(n_max: int = 400) -> tuple[np.ndarray, np.ndarray]:
+    """Relative shell mid-radii r_mid / R_out of every shell grid of the study:
+    for k = 1..n_max shells, the equal-width grid from 0 (external_sphere) and
+    the log-spaced grid from 10 AU (central_source), laid end to end.  Returns
+    the table and start[2, n_max + 1] (start[g, k] = offset of grid g with k shells)."""
+    base = np.zeros(n_max + 2, np.int64)
+    np.cumsum(np.arange(n_max + 1), out=base[1:])
+    tab = np.empty(2 * int(base[-1]), np.float64)
+    for k in range(1, n_max + 1):
+        e = np.linspace(0.0, R_OUT, k + 1)
+        tab[base[k]:base[k + 1]] = 0.5 * (e[1:] + e[:-1]) / e[-1]
+        e = np.geomspace(10 * AU, R_OUT, k + 1)
+        tab[base[-1] + base[k]:base[-1] + base[k + 1]] = 0.5 * (e[1:] + e[:-1]) / e[-1]
+    start = np.stack([base[:-1], base[:-1] + base[-1]])
+    return tab, start
+
+
+def study_model_inputs(params: dict, models=None) -> dict:
+    """Per-model surrogate inputs of a study: model_x [m, 5] float32 (the first
+    five columns of surrogate_features), row offsets [m + 1], and per-model
+    offsets into the shared radius table (column 5)."""
+    idx = np.arange(len(params["n"])) if models is None else np.asarray(models, np.int64)
+    n = params["n"][idx].astype(np.int64)
+    central = params["central"][idx].astype(np.int64)
+    c = central == 1
+    x = np.zeros((len(idx), 5), np.float64)
+    x[:, 0] = np.log10(params["tau_V"][idx])
+    x[:, 1] = params["p"][idx]
+    x[c, 2] = np.log10(params["L"][idx][c] / LSUN)
+    x[~c, 3] = np.log10(params["field_scale"][idx][~c])
+    x[:, 4] = central
+    row_off = np.zeros(len(idx) + 1, np.int64)
+    np.cumsum(n, out=row_off[1:])
+    tab, start = radius_table(int(n.max()) if len(n) else 1)
+    return dict(model_x=x.astype(np.float32), row_off=row_off, radius_off=start[central, n],
+                radius=tab.astype(np.float32))
+
+
+def study_features(params: dict, models=None) -> tuple[np.ndarray, np.ndarray]:
+    """surrogate_features of many models at once: [rows, 6] float32 and the row
+    offsets per model ([len(models) + 1], int64)."""
+    q = study_model_inputs(params, models)
+    n = np.diff(q["row_off"])
+    rows = int(q["row_off"][-1])
+    f = np.empty((rows, 6), np.float32)
+    f[:, :5] = np.repeat(q["model_x"], n, axis=0)
+    local = np.arange(rows, dtype=np.int64) - np.repeat(q["row_off"][:-1], n)
+    f[:, 5] = q["radius"][np.repeat(q["radius_off"], n) + local]
+    return f, q["row_off"]
+
+
+def study_shells(params: dict, models=None) -> tuple[np.ndarray, np.ndarray]:
+    """Shell radii and densities of many study models at once, as batch_model
+    builds them one by one: r_edges of every model end to end ([sum(n + 1)])
+    and rho ([sum(n)])."""
+    idx = np.arange(len(params["n"])) if models is None else np.asarray(models, np.int64)
+    n = params["n"][idx].astype(np.int64)
+    central = params["central"][idx].astype(np.int64)
+    grids = {}
+    for k in np.unique(n):
+        grids[(0, int(k))] = np.linspace(0.0, R_OUT, k + 1)
+        grids[(1, int(k))] = np.geomspace(10 * AU, R_OUT, k + 1)
+    edges = [grids[(int(c), int(k))] for c, k in zip(central, n)]
+    r_flat = np.concatenate(edges) if edges else np.zeros(0)
+    lo = np.concatenate([e[:-1] for e in edges]) if edges else np.zeros(0)
+    hi = np.concatenate([e[1:] for e in edges]) if edges else np.zeros(0)
+    rm = 0.5 * (lo + hi)
+    p = np.repeat(params["p"][idx], n)
+    cen = np.repeat(central, n) == 1
+    shape = np.where(cen, rm ** (-p), (1.0 + (rm / R0_CORE) ** 2) ** (-0.5 * p))
+    off = np.zeros(len(idx), np.int64)
+    np.cumsum(n[:-1], out=off[1:])
+    col = np.add.reduceat(shape * (hi - lo), off) * kappa_ext_V()
+    rho = shape * np.repeat(params["tau_V"][idx] / col, n)
+    return r_flat, rho

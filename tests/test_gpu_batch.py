@@ -5,6 +5,7 @@ import os
 import numpy as np
 import pytest
 
+import mc_stats
 import oracle
 from paper_2408_13807_amd import workloads as wl
 
@@ -33,18 +34,6 @@ def split(b, arr):
     return [arr[b.offsets[j]:b.offsets[j + 1]] for j in range(len(b.offsets) - 1)]
 
 
-def within(T, runs, frac=0.95):
-    """T of one run against an ensemble of runs: within max(1 %, 3 sigma) for
-    `frac` of the shells, and within max(1 %, 5 sigma, ensemble range) for all
-    (rarely hit inner shells have a discrete, often degenerate, spread)."""
-    mean, std = runs.mean(axis=0), runs.std(axis=0, ddof=1)
-    rng = runs.max(axis=0) - runs.min(axis=0)
-    d = np.abs(T - mean)
-    ok3 = d <= np.maximum(0.01 * mean, 3 * std)
-    ok5 = d <= np.maximum(np.maximum(0.01 * mean, 5 * std), rng)
-    return ok3.mean() >= frac and ok5.all(), ok3.mean()
-
-
 def test_batch_matches_single_model_ensembles(ire, params):
     models = pick(params, 24, seed=1)
     scale = 0.02
@@ -55,12 +44,12 @@ def test_batch_matches_single_model_ensembles(ire, params):
     assert s["n_models"] == 24 and s["n_launch"] == sum(max(1, round(int(params["n_pkg"][m]) * scale)) for m in models)
     assert abs((s["escaped"] + s["ffi_escaped"] + s["terminated"]) / s["L_total"] - 1) < 1e-9
     fracs = []
-    for j, (m, T) in enumerate(zip(models, split(b, r["T"]))):
+    for m, T in zip(models, split(b, r["T"])):
         mm = wl.batch_model(params, m)
         key = "n_ps" if params["central"][m] else "n_ext"
         npk = max(1, round(int(params["n_pkg"][m]) * scale))
-        runs = np.stack([ire.run_model(mm, seed=100 + k, **{key: npk})["T"] for k in range(12)])
-        ok, f = within(T, runs)
+        runs = [ire.run_model(mm, seed=100 + k, **{key: npk}) for k in range(16)]
+        ok, f = mc_stats.compare_runs(T, [x["T"] for x in runs], [x["A"] for x in runs], name=f"model {m}")
         fracs.append(f)
         assert ok, (m, f)
     print(f"batch vs single-model ensembles: min {min(fracs) * 100:.1f}% of shells within max(1%, 3 sigma)")
@@ -78,7 +67,7 @@ def test_batch_matches_oracle(ire, params):
         key = "n_ps" if params["central"][m] else "n_ext"
         npk = max(1, round(int(params["n_pkg"][m]) * scale))
         e = oracle.ensemble(mm, seeds=range(1, 17), **{key: npk})
-        ok, f = within(T, e["T"])
+        ok, f = mc_stats.compare_runs(T, e["T"], e["A"], name=f"model {m}")
         print(f"model {m}: {f * 100:.1f}% of shells within max(1%, 3 sigma) of the oracle")
         assert ok
     b.close()

@@ -92,3 +92,51 @@ def test_save_load_roundtrip(sur, tmp_path):
     np.testing.assert_array_equal(a[1], b[1])
     net.close()
     other.close()
+
+
+def test_predict_models_matches_row_prediction(sur):
+    from paper_2408_13807_amd import workloads as wl
+    params = wl.batch_parameters(300, seed=8)
+    X, offs = wl.study_features(params)
+    net = sur.SurNet(members=3, depth=4, seed=11)
+    net.set_normalization(X.mean(axis=0), X.std(axis=0), 1.3, 0.4)
+    mean_r, spread_r = net.predict(X)
+    q = wl.study_model_inputs(params)
+    mean_m, spread_m, ms = net.predict_models(q["model_x"], q["row_off"], q["radius_off"], q["radius"])
+    # the same normalised inputs reach the same kernels: identical results
+    np.testing.assert_array_equal(mean_m, mean_r)
+    np.testing.assert_array_equal(spread_m, spread_r)
+    np.testing.assert_array_equal(ms, np.maximum.reduceat(spread_r, offs[:-1]))
+    # and the FP64 reference forward on a few models
+    P = net.get_params()
+    for m in (0, 17, 299):
+        rows = slice(offs[m], offs[m + 1])
+        ref = np.stack([mlp_ref.predict_logT(P[k].astype(np.float64), 4, X[rows], X.mean(axis=0), X.std(axis=0),
+                                             1.3, 0.4) for k in range(3)]).mean(axis=0)
+        assert np.max(np.abs(mean_m[rows] - ref)) < 2e-2
+    # a subset in another order, with an empty model in between
+    sub = [5, 2, 250]
+    q2 = wl.study_model_inputs(params, sub)
+    ro = np.concatenate([q2["row_off"][:2], q2["row_off"][1:]])
+    ra = np.concatenate([q2["radius_off"][:1], [0], q2["radius_off"][1:]])
+    mx = np.concatenate([q2["model_x"][:1], np.zeros((1, 5), np.float32), q2["model_x"][1:]])
+    mean_s, _, ms_s = net.predict_models(mx, ro, ra, q2["radius"])
+    ref = np.concatenate([mean_r[offs[k]:offs[k + 1]] for k in sub])
+    np.testing.assert_array_equal(mean_s, ref)
+    assert ms_s[1] == 0.0 and ms_s[0] == ms[5] and ms_s[3] == ms[250]
+    net.close()
+
+
+def test_predict_models_rejects_bad_offsets(sur):
+    from paper_2408_13807_amd import ire
+    net = sur.SurNet(members=2, depth=2, seed=1)
+    x = np.zeros((2, 5), np.float32)
+    r = np.linspace(0.1, 0.9, 10).astype(np.float32)
+    for ro, ra in (([1, 3, 6], [0, 0]),       # row_off[0] != 0
+                   ([0, 5, 3], [0, 0]),       # decreasing
+                   ([0, 5, 12], [0, 4]),      # radius range beyond the table
+                   ([0, 5, 8], [-1, 0])):     # negative radius offset
+        with pytest.raises(ire.IREError) as e:
+            net.predict_models(x, np.array(ro), np.array(ra), r)
+        assert e.value.code == ire.IRE_E_INVALID
+    net.close()

@@ -1,0 +1,52 @@
+"""The ensemble criterion of mc_stats on synthetic compound-Poisson shells:
+rare false alarms for runs from the same distribution, and certain detection
+of a 3 % bias."""
+import numpy as np
+
+import mc_stats
+
+
+def draw(rng, lam, runs):
+    """Absorbed energy per shell: Poisson(lam) deposits of Exp(1) energy; T from
+    A^(1/5.8) with a floor, as for dust with kappa ~ nu^1.8."""
+    n = rng.poisson(lam, size=(runs, len(lam)))
+    A = rng.gamma(np.maximum(n, 1), 1.0) * (n > 0)
+    T = np.maximum(30.0 * (A / np.maximum(lam, 1e-9)) ** (1 / 5.8), 3.0)
+    return T, A
+
+
+def test_false_alarm_rate_is_small():
+    rng = np.random.default_rng(5)
+    lam = 10 ** rng.uniform(-0.3, 4, size=200)
+    fails = 0
+    for _ in range(400):
+        T, A = draw(rng, lam, 17)
+        ok, _ = mc_stats.compare_runs(T[0], T[1:], A[1:])
+        fails += not ok
+    assert fails <= 3, fails
+
+
+def test_detects_three_percent_bias():
+    rng = np.random.default_rng(6)
+    lam = 10 ** rng.uniform(-0.3, 4, size=200)
+    for _ in range(50):
+        T, A = draw(rng, lam, 17)
+        ok, _ = mc_stats.compare_runs(1.03 * T[0], T[1:], A[1:])
+        assert not ok
+
+
+def test_detects_one_wrong_well_sampled_shell():
+    rng = np.random.default_rng(7)
+    lam = np.full(100, 5000.0)
+    T, A = draw(rng, lam, 17)
+    t = T[0].copy()
+    t[40] *= 1.05
+    assert mc_stats.compare_runs(T[0], T[1:], A[1:])[0]
+    assert not mc_stats.compare_runs(t, T[1:], A[1:])[0]
+
+
+def test_pooled_sigma_uses_neighbours():
+    mean = np.full(9, 10.0)
+    std = np.array([1, 1, 1, 1, 0.01, 1, 1, 1, 1.0])
+    s = mc_stats.pooled_sigma(mean, std)
+    assert s[4] == 1.0 and np.all(s >= std)

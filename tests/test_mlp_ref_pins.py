@@ -19,10 +19,11 @@ def test_gradients_match_finite_differences():
     xm, xs, ym, ys = np.zeros(6), np.ones(6), 1.2, 0.3
     loss, g = mlp_ref.loss_and_grad(p, depth, X, y, xm, xs, ym, ys)
     rng = np.random.default_rng(1)
-    # first layer inputs beyond the 6 features never see a nonzero input: zero gradient
+    # first layer inputs beyond the 6 features and the derived log-radius input
+    # never see a nonzero input: zero gradient
     W0 = g[:256 * 32].reshape(256, 32)
-    assert np.all(W0[:, 6:] == 0)
-    idx = np.concatenate([rng.integers(0, 256 * 32, 20) // 32 * 32 + rng.integers(0, 6, 20),
+    assert np.all(W0[:, 7:] == 0) and np.any(W0[:, 6] != 0)
+    idx = np.concatenate([rng.integers(0, 256 * 32, 20) // 32 * 32 + rng.integers(0, 7, 20),
                           rng.integers(256 * 32, len(p), 60)])
     h = 1e-6
     for i in idx:
@@ -45,3 +46,10 @@ def test_zero_network_outputs_bias():
     # SiLU(0) = 0 so every hidden activation vanishes; only b_out moves the output
     loss, g = mlp_ref.loss_and_grad(p, depth, X, np.full(5, 1.0 + 2.0 * 0.7), np.zeros(6), np.ones(6), 1.0, 2.0)
     assert loss == 0.0 and np.all(g == 0)
+
+
+def test_derived_log_radius_input():
+    X = np.zeros((3, 6))
+    X[:, 5] = [1.0, 1e-2, 0.0]
+    x = mlp_ref.inputs(X, np.zeros(6), np.ones(6))
+    assert np.allclose(x[:, 6], [1.5, -0.5, -2.5]) and np.all(x[:, 7:] == 0)
