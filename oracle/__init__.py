@@ -42,7 +42,8 @@ class Options(ct.Structure):
     _fields_ = [("k_bg", ct.c_double), ("ffi", ct.c_int32), ("w_floor", ct.c_double),
                 ("max_events", ct.c_uint64), ("table_mode", ct.c_int32),
                 ("acc_bits", ct.c_int32), ("n_batches", ct.c_int32),
-                ("reemit_uniform", ct.c_int32)]
+                ("reemit_uniform", ct.c_int32), ("use_g_E", ct.c_int32), ("g_E", ct.c_double),
+                ("use_g_S", ct.c_int32), ("g_S", ct.c_double), ("k_A", ct.c_double), ("k_S", ct.c_double)]
 
 
 class Stats(ct.Structure):
@@ -78,6 +79,12 @@ def _load():
         lib.or_eval_sampler.restype = ct.c_int
         lib.or_default_options.argtypes = [ct.POINTER(Options)]
         lib.or_scatter_direction.argtypes = [_DP, _DP, ct.c_double, ct.c_double]
+        lib.or_reemit_weighted.argtypes = [ct.c_double, ct.c_int32, ct.c_double, _DP]
+        lib.or_reemit_weighted.restype = ct.c_double
+        lib.or_scatter_weighted.argtypes = [_DP, _DP, ct.c_double, ct.c_double, ct.c_int32, ct.c_double,
+                                            ct.c_double, _DP, _DP]
+        lib.or_ffi_absorption.argtypes = [ct.c_double, ct.c_double, ct.c_double, _DP]
+        lib.or_ffi_absorption.restype = ct.c_double
         _lib = lib
     return _lib
 
@@ -190,3 +197,35 @@ def scatter_direction(x, d, ct_: float, phi: float) -> np.ndarray:
     d = np.array(d, np.float64)
     _load().or_scatter_direction(_dp(x), _dp(d), float(ct_), float(phi))
     return d
+
+
+def reemit_weighted(g_E: float, src: int, u: np.ndarray):
+    """Radial direction cosines and weights of HG(g_E)-weighted re-emission."""
+    lib = _load()
+    out, w = np.zeros(len(u)), np.zeros(len(u))
+    W = ct.c_double()
+    for j, uj in enumerate(np.asarray(u, np.float64)):
+        out[j] = lib.or_reemit_weighted(float(g_E), int(src), float(uj), ct.byref(W))
+        w[j] = W.value
+    return out, w
+
+
+def scatter_weighted(x, d, g: float, g_S: float, src: int, u0: float, u1: float):
+    """(new direction, cos of the scattering angle, weight) of HG(g_S)-weighted scattering."""
+    x = np.ascontiguousarray(x, np.float64)
+    d = np.array(d, np.float64)
+    c, W = ct.c_double(), ct.c_double()
+    _load().or_scatter_weighted(_dp(x), _dp(d), float(g), float(g_S), int(src), float(u0), float(u1),
+                                ct.byref(c), ct.byref(W))
+    return d, c.value, W.value
+
+
+def ffi_absorption(tau0: float, albedo: float, u: np.ndarray):
+    """Extinction depths and weights of the forced first interaction in absorption depth."""
+    lib = _load()
+    out, w = np.zeros(len(u)), np.zeros(len(u))
+    W = ct.c_double()
+    for j, uj in enumerate(np.asarray(u, np.float64)):
+        out[j] = lib.or_ffi_absorption(float(tau0), float(albedo), float(uj), ct.byref(W))
+        w[j] = W.value
+    return out, w

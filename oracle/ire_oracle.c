@@ -260,6 +260,9 @@ static int state_init(ostate *s, const or_model *m, const or_options *o) {
     if (validate(m)) return -1;
     s->m = m;
     if (o) s->o = *o; else or_default_options(&s->o);
+    if (!(s->o.k_A > 0.0) || !(s->o.k_S > 0.0) || !isfinite(s->o.k_A) || !isfinite(s->o.k_S) ||
+        !(fabs(s->o.g_E) < 1.0) || !(fabs(s->o.g_S) < 1.0) || s->o.ffi < 0 || s->o.ffi > 2)
+        return -1;
     int K = m->K, n = m->n, nt = m->n_t;
     s->K = K;
     s->cav = (m->r_edges[0] > 0.0) ? 1 : 0;
@@ -341,6 +344,12 @@ void or_default_options(or_options *o) {
     o->acc_bits = 0;
     o->n_batches = 1;
     o->reemit_uniform = 0;
+    o->use_g_E = 0;
+    o->g_E = 0.0;
+    o->use_g_S = 0;
+    o->g_S = 0.0;
+    o->k_A = 1.0;
+    o->k_S = 1.0;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -369,6 +378,26 @@ static double ffi_depth(double tau0, double u, double *W) {
     double p = -expm1(-tau0);
     *W = p;
     return -log1p(-u * p);
+}
+
+/* Eqs. 10 and 12 with the optical depth counted in absorption only.  The
+ * interaction point is drawn from the truncated exponential in absorption
+ * depth tA in [0, tau0_A); its extinction depth is tA / (1 - a).  The weight
+ * is the ratio of the densities of the interaction point in extinction depth,
+ * e^{-tau} against the drawn (1 - a) e^{-tA} / (1 - e^{-tau0_A}). */
+double or_ffi_absorption(double tau0, double a, double u, double *W) {
+    const double tau0A = tau0 * (1.0 - a);
+    const double pA = -expm1(-tau0A);
+    const double tA = -log1p(-u * pA);
+    const double tau = tA / (1.0 - a);
+    *W = pA / (1.0 - a) * exp(tA - tau);
+    return tau;
+}
+
+/* Henyey-Greenstein probability density of mu = cos(theta), Eq. 6 */
+static double hg_pdf(double g, double mu) {
+    const double q = 1.0 + g * g - 2.0 * g * mu;
+    return 0.5 * (1.0 - g * g) / (q * sqrt(q));
 }
 
 int or_eval_sampler(int32_t which, double param, int64_t n, const double *u, double *out,
@@ -433,6 +462,47 @@ static void scatter_direction(const double *x, double *d, double ct, double ph) 
 
 int or_scatter_direction(const double x[3], double d[3], double ct, double ph) {
     scatter_direction(x, d, ct, ph);
+    return 0;
+}
+
+/* Eq. 6: re-emission cosine mu' about the reference direction from HG(g_E);
+ * the weight is the isotropic density over the HG density at mu'. */
+double or_reemit_weighted(double g_E, int32_t src, double u, double *W) {
+    const double mup = hg_cos(g_E, u);
+    *W = 0.5 / hg_pdf(g_E, mup);
+    return src == 0 ? -mup : mup;
+}
+
+/* Eq. 7 (as the ratio of the two densities): the new direction's cosine mu'
+ * about the reference direction is drawn from HG(g_S), its azimuth about the
+ * radius vector uniformly from the plane of d and x; the weight is the dust's
+ * HG density at the actual scattering angle over HG(g_S) at mu'. */
+int or_scatter_weighted(const double x[3], double d[3], double g, double g_S, int32_t src, double u0,
+                        double u1, double *cos_theta, double *W) {
+    double xh[3], e1[3], e2[3], dn[3];
+    const double r = sqrt(dot3(x, x));
+    if (r > 0.0) { for (int j = 0; j < 3; ++j) xh[j] = x[j] / r; }
+    else { for (int j = 0; j < 3; ++j) xh[j] = d[j]; }
+    const double mu_old = dot3(xh, d);
+    for (int j = 0; j < 3; ++j) e1[j] = d[j] - mu_old * xh[j];
+    const double ne = sqrt(dot3(e1, e1));
+    if (ne > 1e-12) { for (int j = 0; j < 3; ++j) e1[j] /= ne; }
+    else perp_unit(xh, e1);
+    e2[0] = xh[1] * e1[2] - xh[2] * e1[1];
+    e2[1] = xh[2] * e1[0] - xh[0] * e1[2];
+    e2[2] = xh[0] * e1[1] - xh[1] * e1[0];
+    const double mup = hg_cos(g_S, u0);
+    const double mun = src == 0 ? -mup : mup;
+    const double sn = sqrt(fmax(0.0, 1.0 - mun * mun));
+    const double ph = 2.0 * OR_PI * u1;
+    for (int j = 0; j < 3; ++j) dn[j] = mun * xh[j] + sn * (cos(ph) * e1[j] + sin(ph) * e2[j]);
+    double ct = dot3(d, dn);
+    if (ct > 1.0) ct = 1.0;
+    if (ct < -1.0) ct = -1.0;
+    *cos_theta = ct;
+    *W = hg_pdf(g, ct) / hg_pdf(g_S, mup);
+    const double nrm = sqrt(dot3(dn, dn));
+    for (int j = 0; j < 3; ++j) d[j] = dn[j] / nrm;
     return 0;
 }
 
@@ -532,6 +602,14 @@ static void trace_package(const ostate *s, tally_t *t, int src, uint64_t pid, ui
         d[0] = sqrt(fmax(0.0, 1.0 - mu * mu)); d[1] = 0.0; d[2] = mu;
         i = 0;
     }
+    /* free paths drawn from k e^{-k tau} (Eq. 8) carry the weight of the
+     * realised outcome when the flight ends: with two competing clocks, the
+     * factor (1/k) e^{(k-1) tau} of the clock that fired times the survival
+     * ratio e^{(k'-1) tau'} of the one that did not (both survive at escape) */
+    const double kA = s->o.k_A, kS = s->o.k_S;
+    const int kscale = kA != 1.0 || kS != 1.0;
+    int kw;                      /* this flight's free paths are k-scaled */
+    double tA0, tS0;             /* the depths drawn for this flight */
     if (s->o.ffi) {
         double tau0 = ray_depth(s, x, d, i, k);
         if (!(tau0 > 0.0)) {
@@ -541,15 +619,19 @@ static void trace_package(const ostate *s, tally_t *t, int src, uint64_t pid, ui
             return;
         }
         double p;
-        double tau = ffi_depth(tau0, u[2], &p);
+        double tau = s->o.ffi == 2 ? or_ffi_absorption(tau0, s->alb[k], u[2], &p) : ffi_depth(tau0, u[2], &p);
         t->st.ffi_escaped += eps * W * exp(-tau0);
         W *= p;
         if (u[3] < s->alb[k]) { tauS = tau * s->alb[k]; tauA = INFINITY; }
         else { tauA = tau * (1.0 - s->alb[k]); tauS = INFINITY; }
+        kw = 0;
     } else {
-        tauA = -log(u[2]);
-        tauS = -log(u[3]);
+        tauA = -log(u[2]) / kA;
+        tauS = -log(u[3]) / kS;
+        kw = kscale;
     }
+    tA0 = tauA;
+    tS0 = tauS;
     const double W0 = W;
     uint64_t events = 0;
 
@@ -565,6 +647,7 @@ static void trace_package(const ostate *s, tally_t *t, int src, uint64_t pid, ui
             tauS -= chiS * lb;
             i += dir;
             if (i >= s->nsh) {
+                if (kw) W *= exp((kA - 1.0) * (tA0 - tauA) + (kS - 1.0) * (tS0 - tauS));
                 t->st.escaped[src] += eps * W;
                 t->st.n_escape++;
                 if (events == 0) t->st.n_direct++;
@@ -572,6 +655,10 @@ static void trace_package(const ostate *s, tally_t *t, int src, uint64_t pid, ui
             }
             t->st.n_cross++;
             continue;
+        }
+        if (kw) {
+            if (lA <= lS) W *= exp((kA - 1.0) * tA0 + (kS - 1.0) * (tS0 - (tauS - chiS * lA))) / kA;
+            else W *= exp((kS - 1.0) * tS0 + (kA - 1.0) * (tA0 - (tauA - chiA * lS))) / kS;
         }
         if (events >= s->o.max_events) {
             t->st.terminated += eps * W;
@@ -629,22 +716,41 @@ static void trace_package(const ostate *s, tally_t *t, int src, uint64_t pid, ui
                 double rn = cbrt(r0 * r0 * r0 + u2[1] * (r1 * r1 * r1 - r0 * r0 * r0));
                 for (int j = 0; j < 3; ++j) x[j] = rn * xh[j];
             }
-            double mu = 2.0 * u[2] - 1.0, e[3];
+            double mu, e[3];
+            if (s->o.use_g_E) {
+                double wE;
+                mu = or_reemit_weighted(s->o.g_E, src, u[2], &wE);
+                W *= wE;
+            } else {
+                mu = 2.0 * u[2] - 1.0;
+            }
             perp_unit(xh, e);
             double sn = sqrt(fmax(0.0, 1.0 - mu * mu));
             for (int j = 0; j < 3; ++j) d[j] = mu * xh[j] + sn * e[j];
-            tauA = -log(u[3]);
-            tauS = -log(u2[0]);
+            tauA = -log(u[3]) / kA;
+            tauS = -log(u2[0]) / kS;
+            kw = kscale;
+            tA0 = tauA;
+            tS0 = tauS;
         } else {
             /* scattering (Sect. 2.1, Henyey-Greenstein phase function) */
             for (int j = 0; j < 3; ++j) x[j] += lS * d[j];
             t->st.n_scat++;
             next_block(&rs, u);
-            double ct = hg_cos(s->g[k], u[0]);
-            double ph = 2.0 * OR_PI * u[1];
-            scatter_direction(x, d, ct, ph);
-            tauA = -log(u[2]);
-            tauS = -log(u[3]);
+            if (s->o.use_g_S) {
+                double ct, wS;
+                or_scatter_weighted(x, d, s->g[k], s->o.g_S, src, u[0], u[1], &ct, &wS);
+                W *= wS;
+            } else {
+                double ct = hg_cos(s->g[k], u[0]);
+                double ph = 2.0 * OR_PI * u[1];
+                scatter_direction(x, d, ct, ph);
+            }
+            tauA = -log(u[2]) / kA;
+            tauS = -log(u[3]) / kS;
+            kw = kscale;
+            tA0 = tauA;
+            tS0 = tauS;
         }
         if (W < s->o.w_floor * W0) {
             t->st.terminated += eps * W;

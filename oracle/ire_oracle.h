@@ -46,13 +46,20 @@ typedef struct or_model {
 
 typedef struct or_options {
     double k_bg;            /* centre weighting of background directions, Eq. 5; 0.5 = unweighted */
-    int32_t ffi;            /* forced first interaction, Eqs. 9-12 */
+    int32_t ffi;            /* forced first interaction, Eqs. 9-12: 0 off, 1 in extinction optical depth,
+                               2 in absorption optical depth (the stronger variant named after Eq. 12) */
     double w_floor;         /* terminate when W < w_floor * (launch weight) */
     uint64_t max_events;    /* terminate a package that would start event max_events+1 */
     int32_t table_mode;     /* 0: exact T inversion + exact difference spectra; 1: lookup tables */
     int32_t acc_bits;       /* 0: FP64 accumulators; >0: emulate a float with this many significand bits */
     int32_t n_batches;      /* with acc_bits: the two-counter batch scheme of Sect. 2.3 (1 = one counter) */
     int32_t reemit_uniform; /* re-emit at a uniformly random position in the shell volume (Sect. 4) */
+    /* Sect. 2.2, Table 1: weighted sampling of directions and free paths */
+    int32_t use_g_E;        /* re-emission directions from HG(g_E) about the reference direction (Eq. 6) */
+    double g_E;
+    int32_t use_g_S;        /* scattering directions from HG(g_S) about the reference direction (Eq. 7) */
+    double g_S;
+    double k_A, k_S;        /* free paths from k e^{-k tau} (Eq. 8); 1 = unweighted */
 } or_options;
 
 typedef struct or_stats {
@@ -102,6 +109,23 @@ int or_eval_sampler(int32_t which, double param, int64_t n, const double *u, dou
 /* The oracle's scattering rotation (for tests): d is rotated in place by the
  * angle acos(ct) at azimuth ph measured from the plane of d and x. */
 int or_scatter_direction(const double x[3], double d[3], double ct, double ph);
+
+/* Weighted samplers (for tests).  Reference direction: towards the centre
+ * for packages of the external field (src 0), away from it for the point
+ * source (src 1).
+ * or_reemit_weighted: new direction cosine mu' about the reference drawn from
+ *   HG(g_E) with uniform u; returns the radial direction cosine, *W the weight.
+ * or_scatter_weighted: d (unit, at position x) is replaced by a direction whose
+ *   cosine about the reference is drawn from HG(g_S) (u0) at azimuth 2 pi u1
+ *   from the plane of d and x; *cos_theta = cosine between the old and new
+ *   directions, *W = HG(cos_theta; g) / HG(mu'; g_S).
+ * or_ffi_absorption: interaction point of the forced first flight in units of
+ *   absorption depth (tau0 = extinction depth of the ray, albedo a): returns
+ *   the extinction depth of the point, *W its weight. */
+double or_reemit_weighted(double g_E, int32_t src, double u, double *W);
+int or_scatter_weighted(const double x[3], double d[3], double g, double g_S, int32_t src, double u0,
+                        double u1, double *cos_theta, double *W);
+double or_ffi_absorption(double tau0, double albedo, double u, double *W);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,147 @@
+"""Pins of the oracle's weighted sampling (Sect. 2.2, Table 1; Eqs. 6-8 and the
+absorption-depth variant of Eqs. 9-12).
+
+Every weighted sampler must reproduce the expectations of the unweighted law
+it replaces.  The checks use closed forms that do not reuse the oracle's
+formulas: isotropic Legendre moments, the Henyey-Greenstein moments g^l and
+the addition theorem for the new direction after a scattering
+(E[P_l(mu_new)] = g^l P_l(mu_old)), the cumulative law of the interaction
+point of the first flight, first-absorption probabilities of gray spheres with
+scattering (two competing exponential clocks), and the deterministic
+equilibrium of a purely absorbing cloud.
+"""
+import math
+
+import numpy as np
+import pytest
+from numpy.polynomial import legendre
+
+from paper_2408_13807_amd import workloads as wl
+
+
+def midpoints(n):
+    return (np.arange(n) + 0.5) / n
+
+
+def P(l, x):
+    c = np.zeros(l + 1)
+    c[l] = 1.0
+    return legendre.legval(x, c)
+
+
+@pytest.mark.parametrize("g_E", [-0.4, 0.3, 0.8])
+@pytest.mark.parametrize("src", [0, 1])
+def test_reemission_weights_preserve_isotropy(orc, g_E, src):
+    mu, W = orc.reemit_weighted(g_E, src, midpoints(100_000))
+    assert abs(W.mean() - 1) < 1e-3
+    for l in (1, 2, 3):
+        assert abs(np.mean(W * P(l, mu))) < 2e-3, l
+    # positive g_E sends external packages inwards, point-source packages outwards
+    assert (np.mean(mu) < 0) == ((g_E > 0) == (src == 0))
+
+
+@pytest.mark.parametrize("mu_old,g,g_S,src", [(0.9, 0.5, 0.6, 0), (-0.3, 0.5, -0.5, 1), (0.0, 0.0, 0.6, 1),
+                                              (1.0, -0.3, 0.4, 0), (0.5, 0.7, 0.0, 0)])
+def test_scattering_weights_reproduce_hg_and_addition_theorem(orc, mu_old, g, g_S, src):
+    x = np.array([0.0, 0.0, 3e17])
+    d = np.array([math.sqrt(1 - mu_old**2), 0.0, mu_old])
+    n = 300
+    mun, ct, W = [], [], []
+    for u0 in midpoints(n):
+        for u1 in midpoints(n):
+            dn, c, w = orc.scatter_weighted(x, d, g, g_S, src, u0, u1)
+            mun.append(dn[2])
+            ct.append(c)
+            W.append(w)
+            assert abs(np.dot(dn, dn) - 1) < 1e-12 and abs(np.dot(d, dn) - c) < 1e-12
+    mun, ct, W = np.array(mun), np.array(ct), np.array(W)
+    assert abs(W.mean() - 1) < 3e-3
+    for l in (1, 2, 3):
+        assert abs(np.mean(W * P(l, ct)) - g**l) < 4e-3, ("HG moment", l)
+        assert abs(np.mean(W * P(l, mun)) - g**l * P(l, mu_old)) < 4e-3, ("addition theorem", l)
+
+
+@pytest.mark.parametrize("tau0", [0.3, 3.0])
+@pytest.mark.parametrize("albedo", [0.0, 0.4, 0.8])
+def test_ffi_in_absorption_depth(orc, tau0, albedo):
+    u = midpoints(200_000)
+    tau, W = orc.ffi_absorption(tau0, albedo, u)
+    assert np.all(tau <= tau0 * (1 + 1e-12)) and np.all(tau >= 0)
+    # the interaction point of the first flight has the cumulative law 1 - e^-x
+    assert abs(W.mean() - (-math.expm1(-tau0))) < 1e-4
+    for x in (tau0 / 3, 2 * tau0 / 3):
+        assert abs(np.mean(W * (tau < x)) - (-math.expm1(-x))) < 2e-4
+    if albedo == 0.0:
+        t1, w1 = orc.eval_sampler(3, tau0, u)
+        assert np.allclose(tau, t1, rtol=1e-12) and np.allclose(W, w1, rtol=1e-12)
+
+
+def _first_event_probabilities(m, albedo):
+    """Central source in a gray sphere: probability that the first event is an
+    absorption in each shell (extinction depth T along the radial ray)."""
+    chi_ext = m["kabs"][0] / (1 - albedo) * m["rho"]
+    cum = np.concatenate([[0.0], np.cumsum(chi_ext * np.diff(m["r_edges"]))])
+    return (1 - albedo) * (np.exp(-cum[:-1]) - np.exp(-cum[1:]))
+
+
+@pytest.mark.parametrize("opts", [dict(k_A=2.0), dict(k_A=0.5), dict(k_S=2.5), dict(k_A=1.7, k_S=0.6),
+                                  dict(ffi=2), dict(ffi=1)])
+def test_weighted_free_paths_first_absorption(orc, opts):
+    m = wl.gray_model(10, 1.5, external=False, r_in=0.05 * wl.R_OUT)
+    a = 0.4
+    m["albedo"] = np.full(len(m["nu"]), a)
+    p = _first_event_probabilities(m, a)
+    N, R = 40_000, 8
+    fa = np.stack([orc.run(m, n_ps=N, seed=s, first_abs=True, **opts)["first_abs"] / m["L_ps"]
+                   for s in range(1, R + 1)])
+    mean, sem = fa.mean(axis=0), fa.std(axis=0, ddof=1) / math.sqrt(R)
+    assert np.all(np.abs(mean - p) <= 5 * sem + 1e-3 * p), (mean, p, sem)
+
+
+def test_weighted_method_against_brute_force(orc):
+    # the deterministic equilibrium of a purely absorbing cloud (re-emission
+    # spread uniformly over each shell) is unchanged by weighted re-emission
+    # directions and scaled free paths
+    from oracle import bruteforce as bf
+    m = wl.central_source(n=3, tau_V=30.0, p=1.0, r_in=10 * wl.AU)
+    m["albedo"] = np.zeros(64)
+    ref = bf.solve_central(m)
+    e = orc.ensemble(m, n_ps=300_000, seeds=range(1, 9), reemit_uniform=1, use_g_E=1, g_E=0.4, k_A=1.4)
+    mean = e["T"].mean(axis=0)
+    sem = e["T"].std(axis=0, ddof=1) / math.sqrt(8)
+    assert np.all(np.abs(mean - ref["T"]) <= 4.5 * sem + 2e-4 * ref["T"]), (mean, ref["T"], sem)
+
+
+@pytest.mark.parametrize("opts", [dict(use_g_S=1, g_S=0.5), dict(use_g_E=1, g_E=-0.3, use_g_S=1, g_S=-0.4),
+                                  dict(k_A=1.5, k_S=0.7), dict(ffi=2)])
+def test_weighted_runs_match_unweighted(orc, opts):
+    # a scattering cloud: each weighting option leaves the expected temperatures unchanged
+    m = wl.external_sphere(n=20, tau_V=3.0)
+    N = 60_000
+    base = orc.ensemble(m, n_ext=N, seeds=range(1, 9))
+    wtd = orc.ensemble(m, n_ext=N, seeds=range(101, 109), **opts)
+    d = np.abs(wtd["T"].mean(0) - base["T"].mean(0))
+    s = np.sqrt(wtd["T"].var(0, ddof=1) / 8 + base["T"].var(0, ddof=1) / 8)
+    assert np.all(d <= 5 * s + 2e-3 * base["T"].mean(0)), (d, s)
+
+
+def test_rejects_invalid_weights(orc):
+    m = wl.cfg_external_small()
+    for bad in (dict(k_A=0.0), dict(k_S=-1.0), dict(use_g_E=1, g_E=1.0), dict(use_g_S=1, g_S=-1.5), dict(ffi=3)):
+        with pytest.raises(ValueError):
+            orc.run(m, n_ext=10, **bad)
+
+
+@pytest.mark.parametrize("opts", [dict(k_A=2.0), dict(k_A=1.7, k_S=0.6), dict(k_S=2.0), dict(ffi=2)])
+def test_weighted_energy_balance(orc, opts):
+    # every package eventually leaves: the escaped (plus unforced) power equals
+    # the source power in expectation, which weighs the escape factors
+    m = wl.gray_model(10, 1.5, external=False, r_in=0.05 * wl.R_OUT)
+    m["albedo"] = np.full(len(m["nu"]), 0.4)
+    R = 8
+    out = []
+    for s in range(1, R + 1):
+        st = orc.run(m, n_ps=30_000, seed=s, **opts)["stats"]
+        out.append((sum(st["escaped"]) + st["ffi_escaped"] + st["terminated"]) / st["L_ps"])
+    out = np.array(out)
+    assert abs(out.mean() - 1) <= 5 * out.std(ddof=1) / math.sqrt(R) + 1e-4, out
