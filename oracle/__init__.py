@@ -65,7 +65,7 @@ def _load():
             build()
         lib = ct.CDLL(_LIB_PATH)
         lib.or_run.argtypes = [ct.POINTER(Model), ct.POINTER(Options), ct.c_uint64, ct.c_uint64,
-                               ct.c_uint64, _DP, _DP, ct.POINTER(Stats), _DP, _DP]
+                               ct.c_uint64, _DP, _DP, ct.POINTER(Stats), _DP, _DP, _DP, _DP]
         lib.or_run.restype = ct.c_int
         lib.or_philox4x32_10.argtypes = [ct.POINTER(ct.c_uint32), ct.POINTER(ct.c_uint32),
                                          ct.POINTER(ct.c_uint32)]
@@ -116,7 +116,7 @@ def options(**kw) -> Options:
 
 
 def run(model: dict, n_ext: int = 0, n_ps: int = 0, seed: int = 1, reemit: bool = False,
-        first_abs: bool = False, **opts) -> dict:
+        first_abs: bool = False, sed: bool = False, **opts) -> dict:
     """One oracle run; returns A, T, stats and the optional tallies."""
     lib = _load()
     pm = _Pinned(model)
@@ -125,10 +125,12 @@ def run(model: dict, n_ext: int = 0, n_ps: int = 0, seed: int = 1, reemit: bool 
     T = np.zeros(n)
     R = np.zeros(n * K) if reemit else None
     F = np.zeros(n) if first_abs else None
+    S = np.zeros(2 * K) if sed else None
+    SD = np.zeros(2 * K) if sed else None
     st = Stats()
     o = options(**opts)
     rc = lib.or_run(ct.byref(pm.m), ct.byref(o), int(n_ext), int(n_ps), int(seed), _dp(A), _dp(T),
-                    ct.byref(st), _dp(R), _dp(F))
+                    ct.byref(st), _dp(R), _dp(F), _dp(S), _dp(SD))
     if rc != 0:
         raise ValueError(f"oracle rejected the model (code {rc})")
     stats = {f: getattr(st, f) for f, _ in Stats._fields_}
@@ -138,6 +140,9 @@ def run(model: dict, n_ext: int = 0, n_ps: int = 0, seed: int = 1, reemit: bool 
         out["reemit"] = R.reshape(n, K)
     if first_abs:
         out["first_abs"] = F
+    if sed:
+        out["sed"] = S.reshape(2, K)
+        out["sed_direct"] = SD.reshape(2, K)
     return out
 
 

@@ -559,8 +559,17 @@ typedef struct {
     double *Acur;       /* current-batch counters in the two-counter emulation */
     double *reemit;     /* nsh*K or NULL */
     double *first_abs;  /* nsh or NULL */
+    double *sed;        /* 2*K escaped power per source and frequency, or NULL */
+    double *sed_direct; /* 2*K the part that escaped without any event, or NULL */
     or_stats st;
 } tally_t;
+
+/* escaping power of a package of source src at frequency k */
+static void tally_escape(tally_t *t, int K, int src, int k, double e, int direct) {
+    t->st.escaped[src] += e;
+    if (t->sed) t->sed[src * K + k] += e;
+    if (direct && t->sed_direct) t->sed_direct[src * K + k] += e;
+}
 
 static double acc_read(const ostate *s, const tally_t *t, int i) {
     if (s->o.acc_bits > 0 && s->o.n_batches > 1) return round_bits(t->A[i] + t->Acur[i], s->o.acc_bits);
@@ -613,7 +622,7 @@ static void trace_package(const ostate *s, tally_t *t, int src, uint64_t pid, ui
     if (s->o.ffi) {
         double tau0 = ray_depth(s, x, d, i, k);
         if (!(tau0 > 0.0)) {
-            t->st.escaped[src] += eps * W;
+            tally_escape(t, K, src, k, eps * W, 1);
             t->st.n_escape++;
             t->st.n_direct++;
             return;
@@ -621,6 +630,9 @@ static void trace_package(const ostate *s, tally_t *t, int src, uint64_t pid, ui
         double p;
         double tau = s->o.ffi == 2 ? or_ffi_absorption(tau0, s->alb[k], u[2], &p) : ffi_depth(tau0, u[2], &p);
         t->st.ffi_escaped += eps * W * exp(-tau0);
+        /* the unforced fraction leaves unscattered at the launch frequency */
+        if (t->sed) t->sed[src * K + k] += eps * W * exp(-tau0);
+        if (t->sed_direct) t->sed_direct[src * K + k] += eps * W * exp(-tau0);
         W *= p;
         if (u[3] < s->alb[k]) { tauS = tau * s->alb[k]; tauA = INFINITY; }
         else { tauA = tau * (1.0 - s->alb[k]); tauS = INFINITY; }
@@ -648,7 +660,7 @@ static void trace_package(const ostate *s, tally_t *t, int src, uint64_t pid, ui
             i += dir;
             if (i >= s->nsh) {
                 if (kw) W *= exp((kA - 1.0) * (tA0 - tauA) + (kS - 1.0) * (tS0 - tauS));
-                t->st.escaped[src] += eps * W;
+                tally_escape(t, K, src, k, eps * W, events == 0);
                 t->st.n_escape++;
                 if (events == 0) t->st.n_direct++;
                 return;
@@ -762,7 +774,7 @@ static void trace_package(const ostate *s, tally_t *t, int src, uint64_t pid, ui
 
 int or_run(const or_model *m, const or_options *o, uint64_t n_ext, uint64_t n_ps,
            uint64_t seed, double *A, double *T, or_stats *st, double *reemit,
-           double *first_abs) {
+           double *first_abs, double *sed, double *sed_direct) {
     ostate s;
     int rc = state_init(&s, m, o);
     if (rc) return rc;
@@ -778,6 +790,8 @@ int or_run(const or_model *m, const or_options *o, uint64_t n_ext, uint64_t n_ps
     t.Acur = calloc(s.nsh, sizeof(double));
     t.reemit = reemit ? calloc((size_t)s.nsh * K, sizeof(double)) : NULL;
     t.first_abs = first_abs ? calloc(s.nsh, sizeof(double)) : NULL;
+    if (sed) { memset(sed, 0, 2 * (size_t)K * sizeof(double)); t.sed = sed; }
+    if (sed_direct) { memset(sed_direct, 0, 2 * (size_t)K * sizeof(double)); t.sed_direct = sed_direct; }
     if (!t.A || !t.Acur || (reemit && !t.reemit) || (first_abs && !t.first_abs)) {
         free(t.A); free(t.Acur); free(t.reemit); free(t.first_abs);
         state_free(&s);

@@ -75,12 +75,14 @@ typedef struct or_stats {
 void or_default_options(or_options *o);
 
 /* Run n_ext external and n_ps point-source packages with the given seed.
- * A, T: n outputs (absorbed power, temperature).  reemit (n*K) and
- * first_abs (n) are optional tallies (NULL to skip).  Returns 0 or a negative
- * error code for invalid input. */
+ * A, T: n outputs (absorbed power, temperature).  reemit (n*K), first_abs (n),
+ * sed (2*K: escaped power per source and frequency, the unforced FFI fraction
+ * included) and sed_direct (2*K: the part that escaped without any event) are
+ * optional tallies (NULL to skip).  Returns 0 or a negative error code for
+ * invalid input. */
 int or_run(const or_model *m, const or_options *o, uint64_t n_ext, uint64_t n_ps,
            uint64_t seed, double *A, double *T, or_stats *st, double *reemit,
-           double *first_abs);
+           double *first_abs, double *sed, double *sed_direct);
 
 /* Philox4x32-10 (Salmon et al. 2011): out = bijection(ctr) under key. */
 void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
