@@ -45,6 +45,10 @@ WORKLOADS = {
     "batch4096": ("batch_parameters", None,
                   "batched study: 4096 models, shells U{20..400}, tau_V logU(0.1,1000), density exponent U(0,2), "
                   "external or central source, packages logU(1e5,1e7), one persistent launch"),
+    "surrogate1e6": ("batch_parameters", None,
+                     "learned surrogate: MLP 6(+log r) -> 4x256 SiLU -> log10 T, 5-member BF16 ensemble trained on "
+                     "batched IRE runs of the study generator; inference on 1e6 models with IRE fallback where "
+                     "the ensemble spread exceeds 2 %"),
 }
 
 
@@ -125,6 +129,129 @@ def bench_batch(args) -> dict:
     }
 
 
+def bench_surrogate(args) -> dict:
+    """Models/s of surrogate inference with IRE fallback on 1e6 study models,
+    with the surrogate's T error against IRE on held-out models, next to the
+    batched IRE's models/s on a sample of the same models."""
+    import numpy as np
+    import torch
+
+    from paper_2408_13807_amd import surrogate as S, workloads as wl
+
+    env = os.environ.get
+    n_train = int(env("IRE_SUR_TRAIN_MODELS", "200000"))
+    train_scale = float(env("IRE_SUR_TRAIN_SCALE", "0.3"))
+    fit_steps = int(env("IRE_SUR_STEPS", "30000"))
+    n_eval = int(env("IRE_SUR_EVAL_MODELS", "1024"))
+    ref_scale = float(env("IRE_SUR_REF_SCALE", "4.0"))
+    n_inf = int(env("IRE_SUR_MODELS", "1000000"))
+    thr = float(env("IRE_SUR_THRESHOLD", "0.02"))
+    torch.cuda.set_device(0)
+    note = {}
+
+    def say(msg):
+        print(f"[surrogate bench] {msg}", file=sys.stderr, flush=True)
+
+    def chunks(what):
+        return lambda done, total, secs: say(f"{what}: {done}/{total} models, {secs:.1f} s of IRE")
+
+    # training set and fit (one-time cost, reported)
+    pt = wl.batch_parameters(n_train, seed=101)
+    t0 = time.perf_counter()
+    r = S.ire_profiles(pt, np.arange(n_train), package_scale=train_scale, progress=chunks("training data"))
+    X, y = S.training_set(pt, np.arange(n_train), r["T"])
+    t1 = time.perf_counter()
+    say(f"fitting the ensemble on {len(y)} rows, {fit_steps} steps")
+    net = S.fit(X, y, steps=fit_steps, batch=4096, seed=1)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    say(f"fit done in {t2 - t1:.1f} s")
+    note.update(train_models=n_train, train_package_scale=train_scale, train_rows=int(len(y)),
+                train_data_s=t1 - t0, fit_steps=fit_steps, fit_s=t2 - t1,
+                final_loss=[float(v) for v in net.last_loss])
+
+    # accuracy on held-out models against IRE at ref_scale x their budgets
+    pe = wl.batch_parameters(n_eval, seed=202)
+    ev = np.arange(n_eval)
+    ref = S.ire_profiles(pe, ev, package_scale=ref_scale, progress=chunks("reference"))
+    own = S.ire_profiles(pe, ev, package_scale=1.0, progress=chunks("IRE at 1x"))
+    p = S.predict_models(net, pe, ev)
+    Ts = 10.0 ** p["logT"].astype(np.float64)
+    err_s = S.model_errors(Ts, ref["T"], ref["row_off"])      # median over each model's shells
+    err_i = S.model_errors(own["T"], ref["T"], ref["row_off"])
+    acc = p["model_spread"] <= thr
+    err_f = np.where(acc, err_s, err_i)
+    note.update(eval_models=n_eval, eval_reference=f"IRE at {ref_scale:g}x each model's package budget",
+                error_definition="per model: median over its shells of |T - T_ref| / T_ref",
+                accepted_fraction=float(acc.mean()),
+                surrogate_error_median_accepted=float(np.median(err_s[acc])) if acc.any() else None,
+                surrogate_error_p90_accepted=float(np.quantile(err_s[acc], 0.9)) if acc.any() else None,
+                accepted_models_within_2pct=float((err_s[acc] <= 0.02).mean()) if acc.any() else None,
+                after_fallback_models_within_2pct=float((err_f <= 0.02).mean()),
+                ire_1x_error_median=float(np.median(err_i)),
+                ire_1x_models_within_2pct=float((err_i <= 0.02).mean()))
+
+    # timed inference on n_inf models: inputs resident in HBM
+    pi = wl.batch_parameters(n_inf, seed=303)
+    q = wl.study_model_inputs(pi)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    mx, ro, ra, rad = dev(q["model_x"]), dev(q["row_off"]), dev(q["radius_off"]), dev(q["radius"])
+    n_rows = int(q["row_off"][-1])
+    mean = torch.empty(n_rows, dtype=torch.float32, device="cuda")
+    spread = torch.empty_like(mean)
+    mspread = torch.empty(n_inf, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        net.predict_models_dev(n_inf, n_rows, mx.data_ptr(), ro.data_ptr(), ra.data_ptr(), rad.data_ptr(),
+                               len(q["radius"]), mean.data_ptr(), spread.data_ptr(), mspread.data_ptr(), stream=stream)
+    torch.cuda.synchronize()
+    t_pred, t_fb, n_flag = [], [], 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        net.predict_models_dev(n_inf, n_rows, mx.data_ptr(), ro.data_ptr(), ra.data_ptr(), rad.data_ptr(),
+                               len(q["radius"]), mean.data_ptr(), spread.data_ptr(), mspread.data_ptr(), stream=stream)
+        torch.cuda.synchronize()
+        t_pred.append(time.perf_counter() - ts)
+        flagged = np.nonzero(mspread.cpu().numpy() > thr)[0]
+        n_flag = len(flagged)
+        say(f"predicted {n_inf} models in {t_pred[-1]:.2f} s; {n_flag} flagged for the IRE fallback")
+        tf0 = time.perf_counter()
+        if n_flag:
+            S.ire_profiles(pi, flagged, package_scale=1.0, progress=chunks("fallback"))
+        t_fb.append(time.perf_counter() - tf0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    value = n_inf * args.steps / (t1 - t0)
+
+    # plain batched IRE on a sample of the same models (same budgets)
+    rng = np.random.default_rng(0)
+    sample = np.sort(rng.choice(n_inf, 4096, replace=False))
+    ts = time.perf_counter()
+    S.ire_profiles(pi, sample, package_scale=1.0, progress=chunks("batched IRE sample"))
+    ire_mps = len(sample) / (time.perf_counter() - ts)
+    flop = 2.0 * n_rows * net.members * (32 * 256 + (net.depth - 1) * 256 * 256 + 256)
+    pred_s = sum(t_pred) / len(t_pred)
+    achieved = flop / pred_s / 1e12
+    net.close()
+    note.update(inference_models=n_inf, inference_rows=n_rows, predict_s=pred_s,
+                fallback_models=n_flag, fallback_s=sum(t_fb) / len(t_fb),
+                ire_batched_models_per_s=ire_mps, ire_sample="4096 random models of the same 1e6, one batched launch",
+                speedup_vs_batched_ire=value / ire_mps)
+    return {
+        "metric": "models/s (surrogate inference with IRE fallback at 2 % ensemble spread)",
+        "value": value, "unit": "models/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": (t1 - t0) * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": WORKLOADS["surrogate1e6"][2], "models": n_inf},
+        "surrogate": note,
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": achieved / 2500.0, "traffic": None,
+                     "kernel": "sur_predict_kernel (prediction only, dense BF16 MFMA FLOPs of all members)"},
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,6 +267,9 @@ def main() -> int:
 
     if args.workload == "batch4096":
         print(json.dumps(bench_batch(args)), flush=True)
+        return 0
+    if args.workload == "surrogate1e6":
+        print(json.dumps(bench_surrogate(args)), flush=True)
         return 0
 
     import torch

@@ -48,7 +48,8 @@ typedef struct ire_model ire_model;
 
 typedef struct ire_options {
     double k_bg;          /* Eq. 5: background directions mu = u^k_bg with weight 2 k mu^(2-1/k); 0.5 = off */
-    int32_t ffi;          /* Eqs. 9-12: force the first flight from the source to interact (0/1) */
+    int32_t ffi;          /* Eqs. 9-12: force the first flight from the source to interact: 0 off,
+                             1 in extinction optical depth, 2 in absorption optical depth */
     double w_floor;       /* Sect. 2.2.1: stop a package whose weight fell below w_floor * launch weight (1e-10) */
     uint64_t max_events;  /* stop a package that would start event max_events+1 (scatterings + absorptions) */
     int32_t stepping;     /* IRE_FP32 or IRE_FP64 */
@@ -57,6 +58,15 @@ typedef struct ire_options {
     int32_t aggregate;    /* 1: wave-level reduction of absorbed energy before the global atomic; 0: one atomic per lane */
     int32_t batch;        /* lanes of a wave parked at an event before their events are processed together
                              (1..64; 0 = default 32); changes speed, not the distribution of results */
+    /* Sect. 2.2, Table 1: weighted sampling.  Reference direction: towards the
+     * centre for packages of the external field, outwards for the point source. */
+    int32_t use_g_E;      /* Eq. 6: re-emission cosine about the reference direction from HG(g_E), g_E in (-1,1) */
+    double g_E;
+    int32_t use_g_S;      /* Eq. 7: scattering cosine about the reference direction from HG(g_S), weight =
+                             dust HG density at the scattering angle / HG(g_S) density */
+    double g_S;
+    double k_A, k_S;      /* Eq. 8: free paths from k e^{-k tau} (> 0; 1 = unweighted); the weight of a flight
+                             is the fired clock's (1/k) e^{(k-1) tau} times the other's e^{(k'-1) tau'} */
 } ire_options;
 
 typedef struct ire_stats {
@@ -71,7 +81,8 @@ typedef struct ire_stats {
 } ire_stats;
 
 /* Fill *o with the defaults: k_bg 0.5, ffi 0, w_floor 1e-10, max_events 1e6,
- * stepping IRE_FP32, max_lanes 0, reemit_uniform 0, aggregate 1, batch 0. */
+ * stepping IRE_FP32, max_lanes 0, reemit_uniform 0, aggregate 1, batch 0,
+ * use_g_E 0, g_E 0, use_g_S 0, g_S 0, k_A 1, k_S 1. */
 int ire_default_options(ire_options *o);
 
 /* Create a handle bound to HIP device `hip_device`; *out is owned by the caller
@@ -84,13 +95,13 @@ void ire_destroy(ire_model *m);
  * rho[n] >= 0 densities. */
 int ire_set_shells(ire_model *m, int32_t n, const double *r_edges, const double *rho);
 
-/* Eq. 4: K frequencies nu[K] strictly increasing; kappa_abs[K] > 0 absorption
+/* Eq. 4: K (1..255) frequencies nu[K] strictly increasing; kappa_abs[K] > 0 absorption
  * opacity per mass; albedo[K] in [0,1) (kappa_sca = kappa_abs a / (1-a));
  * g[K] in (-1,1) Henyey-Greenstein asymmetry parameter. */
 int ire_set_dust(ire_model *m, int32_t K, const double *nu, const double *kappa_abs,
                  const double *albedo, const double *g);
 
-/* Sect. 2.1 (temperature lookup table): n_t log-spaced points over
+/* Sect. 2.1 (temperature lookup table): n_t (2..65535) log-spaced points over
  * [t_min, t_max]; defaults 3 K, 1600 K, 512. */
 int ire_set_temperature_grid(ire_model *m, double t_min, double t_max, int32_t n_t);
 
@@ -131,6 +142,13 @@ int ire_get_results(ire_model *m, double *absorbed, double *T, ire_stats *stats)
  * tallies, kernel times) without finalizing or copying shell results; the
  * clamp counters n_below/n_above are those of the last finalize. */
 int ire_get_stats(ire_model *m, ire_stats *stats);
+
+/* Escaping spectrum of the current run (synchronises): escaped power per
+ * source and frequency, sed[2][K] (external, then point source; the unforced
+ * fraction of FFI packages included at their launch frequency), and the part
+ * that left without any scattering or absorption, sed_direct[2][K].  Either
+ * pointer may be NULL. */
+int ire_get_sed(ire_model *m, double *sed, double *sed_direct);
 
 /* Device-pointer variant: writes absorbed[n] and T[n] into caller device
  * memory on hip_stream (kept alive by the caller until the work completes). */
@@ -174,6 +192,11 @@ typedef struct ire_batch_options {
     int32_t batch;            /* lanes parked at an event before the wave processes events (0 = 32) */
     uint64_t item_packages;   /* packages per work item; a model is split into items (0 = 65536) */
     int32_t use_graph;        /* 1: replay zero/trace/finalize as a captured HIP graph (default) */
+    int32_t use_g_E;          /* weighted sampling, as ire_options */
+    double g_E;
+    int32_t use_g_S;
+    double g_S;
+    double k_A, k_S;
 } ire_batch_options;
 
 typedef struct ire_batch_stats {
@@ -215,8 +238,9 @@ const char *ire_batch_last_error(const ire_batch *b);
 /* ------------------------------------------------------------------------
  * Learned surrogate of the IRE temperature profile: an ensemble of MLPs
  * mapping 6 inputs (log10 tau_V, density exponent, log10 L/L_sun or 0,
- * log10 external-field scale or 0, source type 0/1, r_mid/R_out) through
- * `depth` hidden layers of width 256 (SiLU) to log10 T of a shell.  BF16
+ * log10 external-field scale or 0, source type 0/1, r_mid/R_out), plus the
+ * derived input log10(max(r_mid/R_out, 1e-4)) + 1.5, through `depth` hidden
+ * layers of width 256 (SiLU) to log10 T of a shell.  BF16
  * weights and matrix-core (MFMA) products with FP32 accumulation; FP32 master
  * weights and Adam.  Trained on temperatures from the IRE tracer, which also
  * serves as the fallback wherever the ensemble's spread is too large.
@@ -245,6 +269,7 @@ int sur_set_normalization(sur_net *s, const float *x_mean, const float *x_std, f
 /* Parameters per member (FP32, the flat layout of the weights, biases, output weights). */
 int64_t sur_param_count(const sur_net *s);
 int sur_get_params(sur_net *s, float *params /* members * sur_param_count */);
+/* The first layer's weights on the padding inputs (columns 7..31 of W_0) are set to zero. */
 int sur_set_params(sur_net *s, const float *params);
 /* Train every member on rows X[n][6] (host), targets log10 T y[n] (host). */
 int sur_train(sur_net *s, const float *X, const float *y, int64_t n, const sur_train_opts *o, void *hip_stream,

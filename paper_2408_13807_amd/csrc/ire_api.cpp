@@ -46,8 +46,11 @@ struct ire_model {
     DevBuf<ire::DustD> dustd;
     DevBuf<float> cdff, Gf, Df;
     DevBuf<double> cdfd, Gd, Dd, invM, lnGd, lnTd;
+    DevBuf<unsigned char> guide;
+    float g_lg0 = 0.0f, g_scale = 0.0f;
     DevBuf<double> A, A_out, T_out;
     DevBuf<ire::DevStats> stats;
+    DevBuf<double> sed;               // 4*K escaping spectrum (total, then unscattered)
     // run state
     bool begun = false;
     unsigned long long n_total[2] = {0, 0};
@@ -110,6 +113,8 @@ int build_tables(ire_model *m) {
     m->lnG = dt.lnG;
 
     std::vector<float> cdff(cdf.begin(), cdf.end()), Gf(G.begin(), G.end()), Df(D.begin(), D.end());
+    std::vector<unsigned char> guide;
+    ire::host::build_guides(dt, cdf.data(), K, guide, m->g_lg0, m->g_scale);
     hipError_t e;
     if ((e = hipSetDevice(m->device)) != hipSuccess) return m->hip_fail(e, "hipSetDevice");
     if ((e = m->shf.upload(shf)) != hipSuccess || (e = m->shd.upload(shd)) != hipSuccess ||
@@ -118,12 +123,12 @@ int build_tables(ire_model *m) {
         (e = m->Gf.upload(Gf)) != hipSuccess || (e = m->Gd.upload(G)) != hipSuccess ||
         (e = m->Df.upload(Df)) != hipSuccess || (e = m->Dd.upload(D)) != hipSuccess ||
         (e = m->invM.upload(invM)) != hipSuccess || (e = m->lnGd.upload(m->lnG)) != hipSuccess ||
-        (e = m->lnTd.upload(m->lnT)) != hipSuccess)
+        (e = m->lnTd.upload(m->lnT)) != hipSuccess || (e = m->guide.upload(guide)) != hipSuccess)
         return e == hipErrorOutOfMemory ? m->fail(IRE_E_NOMEM, "device allocation failed")
                                         : m->hip_fail(e, "table upload");
     if ((e = m->A.ensure((size_t)n * ire::kAccStride)) != hipSuccess ||
         (e = m->A_out.ensure(n)) != hipSuccess || (e = m->T_out.ensure(n)) != hipSuccess ||
-        (e = m->stats.ensure(1)) != hipSuccess)
+        (e = m->stats.ensure(1)) != hipSuccess || (e = m->sed.ensure((size_t)4 * K)) != hipSuccess)
         return m->fail(IRE_E_NOMEM, "device allocation failed: %s", hipGetErrorString(e));
     m->dirty = false;
     return IRE_OK;
@@ -154,6 +159,12 @@ int ire_default_options(ire_options *o) {
     o->reemit_uniform = 0;
     o->aggregate = 1;
     o->batch = 0;
+    o->use_g_E = 0;
+    o->g_E = 0.0;
+    o->use_g_S = 0;
+    o->g_S = 0.0;
+    o->k_A = 1.0;
+    o->k_S = 1.0;
     return IRE_OK;
 }
 
@@ -192,7 +203,7 @@ void ire_destroy(ire_model *m) {
     (void)hipDeviceSynchronize();
     m->shf.release(); m->shd.release(); m->dustf.release(); m->dustd.release();
     m->cdff.release(); m->Gf.release(); m->Df.release(); m->cdfd.release(); m->Gd.release();
-    m->Dd.release(); m->invM.release(); m->lnGd.release(); m->lnTd.release(); m->A.release();
+    m->Dd.release(); m->invM.release(); m->lnGd.release(); m->lnTd.release(); m->guide.release(); m->sed.release(); m->A.release();
     m->A_out.release(); m->T_out.release(); m->stats.release();
     if (m->ev0) (void)hipEventDestroy(m->ev0);
     if (m->ev1) (void)hipEventDestroy(m->ev1);
@@ -222,7 +233,8 @@ int ire_set_shells(ire_model *m, int32_t n, const double *r_edges, const double 
 int ire_set_dust(ire_model *m, int32_t K, const double *nu, const double *kappa_abs,
                  const double *albedo, const double *g) {
     if (!m) return IRE_E_INVALID;
-    if (K < 1 || !nu || !kappa_abs || !albedo || !g) return m->fail(IRE_E_INVALID, "need K >= 1 and all dust arrays");
+    if (K < 1 || K > ire::kMaxGuideK || !nu || !kappa_abs || !albedo || !g)
+        return m->fail(IRE_E_INVALID, "need 1 <= K <= %d and all dust arrays", ire::kMaxGuideK);
     if (!finite_all(nu, K) || !finite_all(kappa_abs, K) || !finite_all(albedo, K) || !finite_all(g, K))
         return m->fail(IRE_E_INVALID, "non-finite dust data");
     for (int k = 0; k < K; ++k) {
@@ -244,8 +256,8 @@ int ire_set_dust(ire_model *m, int32_t K, const double *nu, const double *kappa_
 
 int ire_set_temperature_grid(ire_model *m, double t_min, double t_max, int32_t n_t) {
     if (!m) return IRE_E_INVALID;
-    if (!(t_min > 0.0) || !(t_max > t_min) || !std::isfinite(t_max) || n_t < 2)
-        return m->fail(IRE_E_INVALID, "need 0 < t_min < t_max and n_t >= 2");
+    if (!(t_min > 0.0) || !(t_max > t_min) || !std::isfinite(t_max) || n_t < 2 || n_t > ire::kMaxGuideNt)
+        return m->fail(IRE_E_INVALID, "need 0 < t_min < t_max and 2 <= n_t <= %d", ire::kMaxGuideNt);
     m->t_min = t_min;
     m->t_max = t_max;
     m->n_t = n_t;
@@ -295,7 +307,9 @@ int ire_set_options(ire_model *m, const ire_options *o) {
     if (!(o->w_floor >= 0.0 && o->w_floor < 1.0)) return m->fail(IRE_E_INVALID, "w_floor must be in [0,1)");
     if (o->stepping != IRE_FP32 && o->stepping != IRE_FP64) return m->fail(IRE_E_INVALID, "stepping must be IRE_FP32 or IRE_FP64");
     if (o->max_lanes < 0) return m->fail(IRE_E_INVALID, "max_lanes must be >= 0");
-    if (o->ffi != 0 && o->ffi != 1) return m->fail(IRE_E_INVALID, "ffi must be 0 or 1");
+    if (o->ffi < 0 || o->ffi > 2) return m->fail(IRE_E_INVALID, "ffi must be 0, 1 or 2");
+    const std::string we = ire::host::check_weights(o->use_g_E, o->g_E, o->use_g_S, o->g_S, o->k_A, o->k_S);
+    if (!we.empty()) return m->fail(IRE_E_INVALID, "%s", we.c_str());
     if (o->reemit_uniform != 0 && o->reemit_uniform != 1) return m->fail(IRE_E_INVALID, "reemit_uniform must be 0 or 1");
     if (o->aggregate != 0 && o->aggregate != 1) return m->fail(IRE_E_INVALID, "aggregate must be 0 or 1");
     if (o->batch < 0 || o->batch > 64) return m->fail(IRE_E_INVALID, "batch must be in [0, 64]");
@@ -327,7 +341,8 @@ int ire_begin(ire_model *m, uint64_t n_ext_total, uint64_t n_ps_total, uint64_t 
     m->ms_trace = 0.0f;
     m->ms_finalize = 0.0f;
     m->timed = false;
-    if ((e = ire::launch_zero(m->A.p, (int)m->rho.size(), m->stats.p, 1, nullptr)) != hipSuccess)
+    if ((e = ire::launch_zero(m->A.p, (int)m->rho.size(), m->stats.p, 1, m->sed.p, 4 * (int)m->nu.size(), nullptr)) !=
+        hipSuccess)
         return m->hip_fail(e, "zero accumulators");
     if ((e = hipStreamSynchronize(nullptr)) != hipSuccess) return m->hip_fail(e, "zero accumulators");
     m->begun = true;
@@ -372,20 +387,25 @@ int ire_advance(ire_model *m, uint64_t n_ext, uint64_t n_ps, void *hip_stream) {
     p.shf = m->shf.p; p.dustf = m->dustf.p; p.cdff = m->cdff.p; p.Gf = m->Gf.p; p.Df = m->Df.p;
     p.shd = m->shd.p; p.dustd = m->dustd.p; p.cdfd = m->cdfd.p; p.Gd = m->Gd.p; p.Dd = m->Dd.p;
     p.invM = m->invM.p;
+    p.guide = m->guide.p;
+    p.g_lg0 = m->g_lg0;
+    p.g_scale = m->g_scale;
     p.eps[0] = m->eps[0]; p.eps[1] = m->eps[1];
     p.n_ext = n_ext; p.n_ps = n_ps;
     p.pid0[0] = m->n_done[0]; p.pid0[1] = m->n_done[1];
     p.seed = m->seed;
     p.k_bg = m->opt.k_bg; p.ffi = m->opt.ffi; p.reemit_uniform = m->opt.reemit_uniform;
     p.w_floor = m->opt.w_floor; p.max_events = m->opt.max_events; p.max_lanes = m->opt.max_lanes;
-    p.A = m->A.p; p.stats = m->stats.p;
+    p.use_g_E = m->opt.use_g_E; p.g_E = m->opt.g_E; p.use_g_S = m->opt.use_g_S; p.g_S = m->opt.g_S;
+    p.k_A = m->opt.k_A; p.k_S = m->opt.k_S;
+    p.A = m->A.p; p.stats = m->stats.p; p.sed = m->sed.p;
     {
         const unsigned long long waves = (unsigned long long)grid * (block / 64);
         unsigned long long c = (n_ext + n_ps) / (waves * 8ull);
         p.chunk = std::min<unsigned long long>(std::max<unsigned long long>(c, 64ull), 4096ull);
     }
     p.batch = m->opt.batch > 0 ? m->opt.batch : 32;
-    if ((e = ire::launch_zero(nullptr, n, m->stats.p, 0, s)) != hipSuccess) return m->hip_fail(e, "cursor reset");
+    if ((e = ire::launch_zero(nullptr, n, m->stats.p, 0, nullptr, 0, s)) != hipSuccess) return m->hip_fail(e, "cursor reset");
     if ((e = hipEventRecord(m->ev0, s)) != hipSuccess) return m->hip_fail(e, "event");
     if ((e = ire::launch_trace(p, fp64, m->opt.aggregate, grid, block, lds, s)) != hipSuccess)
         return m->hip_fail(e, "trace launch");
@@ -508,6 +528,21 @@ int ire_get_stats(ire_model *m, ire_stats *stats) {
     if ((e = hipMemcpy(&hs, m->stats.p, sizeof(hs), hipMemcpyDeviceToHost)) != hipSuccess)
         return m->hip_fail(e, "stats copy");
     fill_stats(m, hs, stats);
+    return IRE_OK;
+}
+
+int ire_get_sed(ire_model *m, double *sed, double *sed_direct) {
+    if (!m) return IRE_E_INVALID;
+    if (!m->begun) return m->fail(IRE_E_STATE, "no run to report");
+    const size_t K = m->nu.size();
+    hipError_t e;
+    if ((e = hipSetDevice(m->device)) != hipSuccess) return m->hip_fail(e, "hipSetDevice");
+    if ((e = hipStreamSynchronize(m->last_stream)) != hipSuccess) return m->hip_fail(e, "synchronize");
+    std::vector<double> h(4 * K);
+    if ((e = hipMemcpy(h.data(), m->sed.p, h.size() * sizeof(double), hipMemcpyDeviceToHost)) != hipSuccess)
+        return m->hip_fail(e, "spectrum copy");
+    if (sed) std::copy(h.begin(), h.begin() + 2 * K, sed);
+    if (sed_direct) std::copy(h.begin() + 2 * K, h.end(), sed_direct);
     return IRE_OK;
 }
 

@@ -45,6 +45,8 @@ struct ire_batch {
     DevBuf<ire::ShellF> shells;
     DevBuf<ire::DustF> dustf;
     DevBuf<float> cdff, Gf, Df;
+    DevBuf<unsigned char> guide;
+    float g_lg0 = 0.0f, g_scale = 0.0f;
     DevBuf<double> Gd, lnG, lnT, invM, A, A_out, T_out;
     DevBuf<ire::BatchModelDev> models_d;
     DevBuf<ire::BatchItemDev> items_d;
@@ -82,7 +84,8 @@ namespace {
 size_t lds_bytes(const ire_batch *b) {
     const int K = (int)b->nu.size();
     return (size_t)b->max_table * sizeof(ire::ShellF) + (size_t)K * sizeof(ire::DustF) +
-           (size_t)2 * K * sizeof(float) + (size_t)b->n_t * sizeof(float) + (size_t)b->n_t * K * sizeof(float);
+           (size_t)2 * K * sizeof(float) + (size_t)b->n_t * sizeof(float) + (size_t)b->n_t * K * sizeof(float) +
+           ire::guide_bytes(b->n_t);
 }
 
 // Build all tables, the per-model records and the ordered work items; upload.
@@ -174,6 +177,8 @@ int prepare(ire_batch *b) {
         return b->fail(IRE_E_INVALID, "tables need %zu bytes of LDS, the device has %zu", lds_bytes(b), b->max_lds);
 
     std::vector<float> cdff(cdf.begin(), cdf.end()), Gf(b->dt.G.begin(), b->dt.G.end()), Df(b->dt.D.begin(), b->dt.D.end());
+    std::vector<unsigned char> guide;
+    ire::host::build_guides(b->dt, cdf.data(), K, guide, b->g_lg0, b->g_scale);
     hipError_t he;
     if ((he = hipSetDevice(b->device)) != hipSuccess) return b->hip_fail(he, "hipSetDevice");
     if ((he = b->shells.upload(shf)) != hipSuccess || (he = b->dustf.upload(b->dt.df)) != hipSuccess ||
@@ -181,7 +186,7 @@ int prepare(ire_batch *b) {
         (he = b->Df.upload(Df)) != hipSuccess || (he = b->Gd.upload(b->dt.G)) != hipSuccess ||
         (he = b->lnG.upload(b->dt.lnG)) != hipSuccess || (he = b->lnT.upload(b->dt.lnT)) != hipSuccess ||
         (he = b->invM.upload(invM)) != hipSuccess || (he = b->models_d.upload(b->mdev)) != hipSuccess ||
-        (he = b->items_d.upload(b->items)) != hipSuccess)
+        (he = b->items_d.upload(b->items)) != hipSuccess || (he = b->guide.upload(guide)) != hipSuccess)
         return he == hipErrorOutOfMemory ? b->fail(IRE_E_NOMEM, "device allocation failed") : b->hip_fail(he, "upload");
     if ((he = b->A.ensure(b->n_shells * ire::kAccStride)) != hipSuccess || (he = b->A_out.ensure(b->n_shells)) != hipSuccess ||
         (he = b->T_out.ensure(b->n_shells)) != hipSuccess || (he = b->stats.ensure(1)) != hipSuccess)
@@ -204,6 +209,9 @@ int enqueue(ire_batch *b, hipStream_t s) {
     p.Gf = b->Gf.p;
     p.Df = b->Df.p;
     p.invM = b->invM.p;
+    p.guide = b->guide.p;
+    p.g_lg0 = b->g_lg0;
+    p.g_scale = b->g_scale;
     p.A = b->A.p;
     p.models = b->models_d.p;
     p.items = b->items_d.p;
@@ -213,6 +221,12 @@ int enqueue(ire_batch *b, hipStream_t s) {
     p.batch = b->opt.batch > 0 ? b->opt.batch : 32;
     p.w_floor = b->opt.w_floor;
     p.max_events = b->opt.max_events;
+    p.use_g_E = b->opt.use_g_E;
+    p.g_E = b->opt.g_E;
+    p.use_g_S = b->opt.use_g_S;
+    p.g_S = b->opt.g_S;
+    p.k_A = b->opt.k_A;
+    p.k_S = b->opt.k_S;
     p.stats = b->stats.p;
     const size_t lds = lds_bytes(b);
     hipError_t e;
@@ -327,6 +341,12 @@ int ire_batch_default_options(ire_batch_options *o) {
     o->batch = 0;
     o->item_packages = 65536;
     o->use_graph = 1;
+    o->use_g_E = 0;
+    o->g_E = 0.0;
+    o->use_g_S = 0;
+    o->g_S = 0.0;
+    o->k_A = 1.0;
+    o->k_S = 1.0;
     return IRE_OK;
 }
 
@@ -361,7 +381,7 @@ void ire_batch_destroy(ire_batch *b) {
     (void)hipDeviceSynchronize();
     b->drop_graph();
     b->shells.release(); b->dustf.release(); b->cdff.release(); b->Gf.release(); b->Df.release();
-    b->Gd.release(); b->lnG.release(); b->lnT.release(); b->invM.release(); b->A.release();
+    b->Gd.release(); b->lnG.release(); b->lnT.release(); b->invM.release(); b->guide.release(); b->A.release();
     b->A_out.release(); b->T_out.release(); b->models_d.release(); b->items_d.release(); b->stats.release();
     if (b->cap) (void)hipStreamDestroy(b->cap);
     if (b->ev0) (void)hipEventDestroy(b->ev0);
@@ -388,8 +408,8 @@ int ire_batch_set_dust(ire_batch *b, int32_t K, const double *nu, const double *
 
 int ire_batch_set_temperature_grid(ire_batch *b, double t_min, double t_max, int32_t n_t) {
     if (!b) return IRE_E_INVALID;
-    if (!(t_min > 0.0) || !(t_max > t_min) || !std::isfinite(t_max) || n_t < 2)
-        return b->fail(IRE_E_INVALID, "need 0 < t_min < t_max and n_t >= 2");
+    if (!(t_min > 0.0) || !(t_max > t_min) || !std::isfinite(t_max) || n_t < 2 || n_t > ire::kMaxGuideNt)
+        return b->fail(IRE_E_INVALID, "need 0 < t_min < t_max and 2 <= n_t <= %d", ire::kMaxGuideNt);
     b->t_min = t_min;
     b->t_max = t_max;
     b->n_t = n_t;
@@ -450,7 +470,9 @@ int ire_batch_set_options(ire_batch *b, const ire_batch_options *o) {
     if (!o) return b->fail(IRE_E_INVALID, "null options");
     if (!(o->k_bg > 0.0 && o->k_bg <= 1.0)) return b->fail(IRE_E_INVALID, "k_bg must be in (0,1]");
     if (!(o->w_floor >= 0.0 && o->w_floor < 1.0)) return b->fail(IRE_E_INVALID, "w_floor must be in [0,1)");
-    if (o->ffi != 0 && o->ffi != 1) return b->fail(IRE_E_INVALID, "ffi must be 0 or 1");
+    if (o->ffi < 0 || o->ffi > 2) return b->fail(IRE_E_INVALID, "ffi must be 0, 1 or 2");
+    const std::string we = ire::host::check_weights(o->use_g_E, o->g_E, o->use_g_S, o->g_S, o->k_A, o->k_S);
+    if (!we.empty()) return b->fail(IRE_E_INVALID, "%s", we.c_str());
     if (o->reemit_uniform != 0 && o->reemit_uniform != 1) return b->fail(IRE_E_INVALID, "reemit_uniform must be 0 or 1");
     if (o->aggregate != 0 && o->aggregate != 1) return b->fail(IRE_E_INVALID, "aggregate must be 0 or 1");
     if (o->batch < 0 || o->batch > 64) return b->fail(IRE_E_INVALID, "batch must be in [0, 64]");

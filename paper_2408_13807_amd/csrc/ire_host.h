@@ -104,6 +104,36 @@ inline std::string build_dust_tables(const std::vector<double> &nu, const std::v
     return "";
 }
 
+// Guide tables for the G(T) table and the frequency CDFs (layout in
+// ire_internal.h).  Any start is correct for the device's bidirectional
+// scan; a good start makes the scan one or two steps.
+inline void build_guides(const DustTables &dt, const double *src_cdf /* 2*K */, int K, std::vector<unsigned char> &out,
+                         float &lg0, float &scale) {
+    const int nt = (int)dt.G.size();
+    out.assign(guide_bytes(nt), 0);
+    auto count_le = [](const double *t, int n, double x) {
+        int c = 0;
+        while (c < n && t[c] <= x) ++c;
+        return c;
+    };
+    const double l0 = std::log2(dt.G[0]), l1 = std::log2(dt.G[nt - 1]);
+    lg0 = (float)l0;
+    scale = l1 > l0 ? (float)(nt / (l1 - l0)) : 0.0f;
+    uint16_t *gg = reinterpret_cast<uint16_t *>(out.data());
+    for (int b = 0; b < nt; ++b) {
+        const double edge = std::exp2(l0 + (scale > 0.0f ? b / (double)scale : 0.0));
+        gg[b] = (uint16_t)count_le(dt.G.data(), nt, edge);
+    }
+    unsigned char *dg = out.data() + (size_t)nt * 2;
+    for (int j = 0; j < nt; ++j)
+        for (int b = 0; b < kGuide; ++b)
+            dg[(size_t)j * kGuide + b] = (unsigned char)count_le(dt.D.data() + (size_t)j * K, K, (double)b / kGuide);
+    unsigned char *cg = dg + (size_t)nt * kGuide;
+    for (int s = 0; s < 2; ++s)
+        for (int b = 0; b < kGuide; ++b)
+            cg[s * kGuide + b] = (unsigned char)count_le(src_cdf + (size_t)s * K, K, (double)b / kGuide);
+}
+
 // Shell table of one cloud in units of its outer radius: [an empty cavity
 // shell when r_edges[0] > 0], the n shells, and a sentinel beyond the surface
 // with infinite density.  invM gets the n reciprocal shell masses.
@@ -170,8 +200,16 @@ inline bool finite_all(const double *a, size_t n) {
 }
 
 // Argument checks shared by the single-model and batched setters; "" = valid.
+// Weighted-sampling options (Table 1): "" or what is wrong.
+inline std::string check_weights(int use_g_E, double g_E, int use_g_S, double g_S, double k_A, double k_S) {
+    if ((use_g_E != 0 && use_g_E != 1) || (use_g_S != 0 && use_g_S != 1)) return "use_g_E and use_g_S must be 0 or 1";
+    if (!(std::fabs(g_E) < 1.0) || !(std::fabs(g_S) < 1.0)) return "g_E and g_S must be in (-1, 1)";
+    if (!(k_A > 0.0) || !(k_S > 0.0) || !std::isfinite(k_A) || !std::isfinite(k_S)) return "k_A and k_S must be finite and > 0";
+    return "";
+}
+
 inline std::string check_dust(int K, const double *nu, const double *kabs, const double *albedo, const double *g) {
-    if (K < 1 || !nu || !kabs || !albedo || !g) return "need K >= 1 and all dust arrays";
+    if (K < 1 || K > kMaxGuideK || !nu || !kabs || !albedo || !g) return "need 1 <= K <= 255 and all dust arrays";
     if (!finite_all(nu, K) || !finite_all(kabs, K) || !finite_all(albedo, K) || !finite_all(g, K))
         return "non-finite dust data";
     for (int k = 0; k < K; ++k) {

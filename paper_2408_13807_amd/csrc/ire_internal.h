@@ -13,6 +13,16 @@ constexpr int kAccStride = 16;
 // density): a flight that leaves the cloud ends in the first; the second keeps
 // the tracer's one-record-ahead reads inside the table for every lane.
 constexpr int kSentinels = 2;
+// Guide tables (cut-point method, Chen & Asau 1974) accelerate the searches
+// of the G(T) table and of the frequency CDFs; the searches stay exact (a
+// bidirectional scan from the guide's start).  Layout of the guide bytes:
+// uint16 gg[n_t] (G table, bins uniform in log2 G), then uint8
+// dg[n_t][kGuide] (re-emission CDF rows, bins uniform in u), then uint8
+// cg[2][kGuide] (source CDFs).
+constexpr int kGuide = 16;
+__host__ __device__ inline size_t guide_bytes(int n_t) { return ((size_t)n_t * 2 + (size_t)n_t * kGuide + 2 * kGuide + 15) / 16 * 16; }
+constexpr int kMaxGuideK = 255;       // frequencies per CDF row a byte guide can index
+constexpr int kMaxGuideNt = 65535;    // temperature points a 16-bit guide can index
 
 // Shell geometry in units of the outer radius: squared inner and outer radius,
 // density times the outer radius (so kappa * rho_hat * l_hat is an optical depth
@@ -54,6 +64,8 @@ struct TraceParams {
     const double *Gd;
     const double *Dd;
     const double *invM;               // n: 1 / shell mass
+    const unsigned char *guide;       // guide_bytes(n_t) (staged into LDS by the FP32 path)
+    float g_lg0, g_scale;             // G guide bin = (log2 a - g_lg0) * g_scale
     double eps[2];                    // package energy per source
     unsigned long long n_ext, n_ps;   // packages of this launch per source
     unsigned long long pid0[2];       // first package id per source (chunked runs)
@@ -63,10 +75,13 @@ struct TraceParams {
     int reemit_uniform;
     double w_floor;
     unsigned long long max_events;
+    int use_g_E, use_g_S;             // weighted sampling (Table 1)
+    double g_E, g_S, k_A, k_S;
     int max_lanes;                    // 0 = no limit
     unsigned long long chunk;         // package indices a wave takes from the cursor at once (>= 64)
     int batch;                        // parked lanes that trigger an event pass (1..64)
     double *A;                        // n accumulators, stride kAccStride
+    double *sed;                      // 4*K: escaped power per source and frequency, then its unscattered part
     DevStats *stats;
 };
 
@@ -103,6 +118,8 @@ struct BatchParams {
     const DustF *dustf;
     const float *cdff;                // 2*K source CDFs (external field, point source)
     const float *Gf, *Df;
+    const unsigned char *guide;       // guide_bytes(n_t)
+    float g_lg0, g_scale;
     const double *invM;               // per shell, flat
     double *A;                        // per shell, flat, stride kAccStride
     const BatchModelDev *models;
@@ -111,6 +128,8 @@ struct BatchParams {
     int ffi, reemit_uniform, batch, pad;
     double w_floor;
     unsigned long long max_events;
+    int use_g_E, use_g_S;             // weighted sampling (Table 1)
+    double g_E, g_S, k_A, k_S;
     DevStats *stats;                  // stats->cursor counts taken items
 };
 
@@ -122,11 +141,12 @@ struct BatchFinalizeParams {
     DevStats *stats;
 };
 
-size_t trace_lds_bytes(int n_table, int K, int n_t);  // n_table = cavity + n + 1
+size_t trace_lds_bytes(int n_table, int K, int n_t);  // n_table = cavity + n + kSentinels
+size_t sed_lds_bytes(int K);
 hipError_t launch_trace(const TraceParams &p, int fp64, int aggregate, int grid, int block,
                         size_t lds, hipStream_t s);
 hipError_t trace_configure(int fp64, int aggregate, size_t lds);
-hipError_t launch_zero(double *A, int n, DevStats *st, int clear_counts, hipStream_t s);
+hipError_t launch_zero(double *A, int n, DevStats *st, int clear_counts, double *sed, int n_sed, hipStream_t s);
 hipError_t launch_finalize(const FinalizeParams &p, hipStream_t s);
 hipError_t batch_configure(int aggregate, size_t lds);
 hipError_t launch_trace_batch(const BatchParams &p, int aggregate, int grid, size_t lds, hipStream_t s);

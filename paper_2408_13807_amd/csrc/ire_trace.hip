@@ -94,6 +94,7 @@ template <> struct P<float> {
     static __device__ __forceinline__ float log1p_(float x) { return log1pf(x); }
     static __device__ __forceinline__ float cbrt_(float x) { return cbrtf(x); }
     static __device__ __forceinline__ float inf() { return __builtin_huge_valf(); }
+    static __device__ __forceinline__ float exp_(float x) { return __expf(x); }
 };
 
 template <> struct P<double> {
@@ -110,6 +111,7 @@ template <> struct P<double> {
     static __device__ __forceinline__ double log1p_(double x) { return log1p(x); }
     static __device__ __forceinline__ double cbrt_(double x) { return cbrt(x); }
     static __device__ __forceinline__ double inf() { return __builtin_huge_val(); }
+    static __device__ __forceinline__ double exp_(double x) { return exp(x); }
 };
 
 // Number of entries of the non-decreasing table t[0..n) that are <= x.
@@ -123,6 +125,46 @@ __device__ __forceinline__ int count_le(const T *t, int n, X x) {
         if (q <= n && (X)t[q - 1] <= x) pos = q;
     }
     return pos;
+}
+
+// Number of entries of the increasing table t[0..n) that are <= x, found by
+// scanning from a starting guess in either direction (exact for any start in
+// [0, n]; a guide table makes the scan short).
+template <typename T, typename X>
+__device__ __forceinline__ int count_le_from(const T *t, int n, X x, int pos) {
+    while (pos > 0 && (X)t[pos - 1] > x) --pos;
+    while (pos < n && (X)t[pos] <= x) ++pos;
+    return pos;
+}
+
+// Guide start for a in the G(T) table: bins uniform in log2 a.
+__device__ __forceinline__ int g_guide(const uint16_t *gg, int n_t, float lg0, float scale, float a) {
+    const float x = (__log2f(a) - lg0) * scale;
+    const int b = x > 0.0f ? (x < (float)(n_t - 1) ? (int)x : n_t - 1) : 0;
+    return gg[b];
+}
+
+// Guide start for u in (0, 1) in a CDF row with kGuide bins.
+template <typename R>
+__device__ __forceinline__ int cdf_guide(const unsigned char *g, R u) {
+    const int b = (int)(u * (R)kGuide);
+    return g[b < kGuide ? b : kGuide - 1];
+}
+
+// Henyey-Greenstein: cos(theta) by inversion of the cumulative law for uniform
+// u, and the probability density of cos(theta) (Eq. 6).
+template <typename R>
+__device__ __forceinline__ R hg_cos(R g, R u) {
+    if (g > (R)-1e-6 && g < (R)1e-6) return (R)2 * u - (R)1;
+    const R f = ((R)1 - g * g) * P<R>::rcp((R)1 - g + (R)2 * g * u);
+    const R c = ((R)1 + g * g - f * f) * P<R>::rcp((R)2 * g);
+    return c > (R)1 ? (R)1 : (c < (R)-1 ? (R)-1 : c);
+}
+
+template <typename R>
+__device__ __forceinline__ R hg_pdf(R g, R mu) {
+    const R q = (R)1 + g * g - (R)2 * g * mu;
+    return (R)0.5 * ((R)1 - g * g) * P<R>::rcp(q * P<R>::sqrt_(q));
 }
 
 // ---------------------------------------------------------------------------
@@ -234,17 +276,22 @@ struct MethodOpts {
     int ffi, reemit_uniform, batch;
     double w_floor;
     unsigned long long max_events;
+    // weighted sampling (Table 1): HG re-emission / scattering directions
+    // about the reference direction, scaled free paths
+    int use_g_E, use_g_S;
+    double g_E, g_S, k_A, k_S;
 };
 
 // Trace every package of one model with the lanes of this wave.  Package
 // indices come from `cursor` (global or LDS memory) `chunk` at a time; the
 // call returns when the cursor is exhausted and every lane is idle.
-template <typename R, bool AGG>
+template <typename R, bool AGG, bool WTD>
 __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodOpts &o,
                                             const typename P<R>::Dust *dust, const R *cdf,
                                             const R *G, const R *D, int K, int n_t,
+                                            const unsigned char *guide, float g_lg0, float g_scale,
                                             unsigned long long *cursor, unsigned long long chunk,
-                                            bool lane_off, LaneCounters &lc) {
+                                            bool lane_off, LaneCounters &lc, double *sed) {
     using Shell = typename P<R>::Shell;
     using Dust = typename P<R>::Dust;
     // lane status: in flight, parked at an interaction (or at the surface),
@@ -261,6 +308,9 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
     const int lane = __lane_id();
     const int batch = o.batch > 0 ? o.batch : 1;
     const Shell *const sentinel = sh + n_int;
+    const uint16_t *const gguide = reinterpret_cast<const uint16_t *>(guide);
+    const unsigned char *const dguide = guide + (size_t)n_t * 2;
+    const unsigned char *const cguide = dguide + (size_t)n_t * kGuide;
 
     unsigned long long pool_next = 0, pool_end = 0;  // wave-uniform
 
@@ -275,6 +325,13 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
     bool ev_abs = false;           // that interaction is an absorption (else a scattering)
     uint32_t pid_lo = 0, pid_hi = 0, blk = 0;
     unsigned long long events = 0;
+    // scaled free paths (Eq. 8): the flight's drawn column and whether its
+    // free paths were scaled (not for the forced first flight)
+    const bool kscale = WTD && (o.k_A != 1.0 || o.k_S != 1.0);
+    const R kA1 = (R)(o.k_A - 1.0), kS1 = (R)(o.k_S - 1.0);
+    const R inv_kA = (R)(1.0 / o.k_A), inv_kS = (R)(1.0 / o.k_S);
+    R sig0 = 0;
+    bool kw = false;
 
     // One boundary step of a package in flight (Eq. 4), computed for every
     // lane and committed only where the package is in flight.  Both free
@@ -322,11 +379,27 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
             // a parked package still stands where its last step began: move it
             // along the column left to the interaction point
             if (st == ST_EVT) t += sig * cur.inv_rho;
+            // scaled free paths: the weight of the flight's outcome, the fired
+            // clock's (1/k) e^{(k-1) tau} times the survival ratio e^{(k'-1) tau'}
+            // of the other (both survival ratios at escape); tau = kappa x column
+            if (WTD && kscale && st == ST_EVT && kw) {
+                const Dust dk = dust[k];
+                const bool esc = ps == sentinel;
+                const R c = esc ? sig0 - sig : sig0;
+                R f = P<R>::exp_((kA1 * dk.kA + kS1 * dk.kS) * c);
+                if (!esc) f *= ev_abs ? inv_kA : inv_kS;
+                W *= f;
+            }
             if (st == ST_EVT) {
                 if (ps == sentinel) {
                     // the flight left the cloud (the step into the sentinel is no crossing)
                     const double e = eps * (double)W;
                     if (src == 0) lc.esc0 += e; else lc.esc1 += e;
+                    if (sed) {
+                        // escaping spectrum per source and frequency (LDS, this workgroup)
+                        atomicAdd(&sed[src * K + k], e);
+                        if (events == 0) atomicAdd(&sed[2 * K + src * K + k], e);
+                    }
                     lc.escape++;
                     lc.cross--;
                     if (events == 0) lc.direct++;
@@ -396,13 +469,16 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
             int row = 0;
             if (absorbing) {
                 const double astar = (A_before + (((double)r1.x + 0.5) * 0x1p-32) * E) * invM;
-                row = count_le(G, n_t, (R)astar);
+                const R a = (R)astar;
+                row = count_le_from(G, n_t, a, g_guide(gguide, n_t, g_lg0, g_scale, (float)a));
                 if (row > n_t - 1) { row = n_t - 1; lc.reabove++; }
                 lc.abs++;
             }
             if (launching || absorbing) {
                 const R *tab = launching ? cdf + src * K : D + (size_t)row * K;
-                k = min(count_le(tab, K, P<R>::uni(launching ? r1.x : r1.y)), K - 1);
+                const unsigned char *gd = launching ? cguide + src * kGuide : dguide + (size_t)row * kGuide;
+                const R u = P<R>::uni(launching ? r1.x : r1.y);
+                k = min(count_le_from(tab, K, u, cdf_guide(gd, u)), K - 1);
             }
             const Dust d = dust[k];
 
@@ -412,7 +488,17 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
                 R rr = P<R>::sqrt_(r2);
                 R mun;
                 if (absorbing) {
-                    mun = (R)2 * P<R>::uni(r1.z) - (R)1;
+                    if (WTD && o.use_g_E) {
+                        // Eq. 6: cosine about the reference direction (inwards for the
+                        // external field, outwards for the point source) from HG(g_E),
+                        // weight = isotropic density / HG density
+                        const R gE = (R)o.g_E;
+                        const R mup = hg_cos(gE, P<R>::uni(r1.z));
+                        W *= (R)0.5 * P<R>::rcp(hg_pdf(gE, mup));
+                        mun = src == 0 ? -mup : mup;
+                    } else {
+                        mun = (R)2 * P<R>::uni(r1.z) - (R)1;
+                    }
                     if (o.reemit_uniform) {
                         const Shell s = cur;
                         const R rin = P<R>::sqrt_(s.r2_in);
@@ -423,30 +509,37 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
                     }
                 } else {
                     lc.scat++;
-                    const R gg = d.g;
                     const R mu = rr > (R)0 ? t * P<R>::rcp(rr) : (R)1;
-                    const R u0 = P<R>::uni(r1.x);
-                    R ct;
-                    if (gg > (R)-1e-6 && gg < (R)1e-6) {
-                        ct = (R)2 * u0 - (R)1;
-                    } else {
-                        const R f = ((R)1 - gg * gg) * P<R>::rcp((R)1 - gg + (R)2 * gg * u0);
-                        ct = ((R)1 + gg * gg - f * f) * P<R>::rcp((R)2 * gg);
-                        ct = ct > (R)1 ? (R)1 : (ct < (R)-1 ? (R)-1 : ct);
-                    }
-                    const R st2 = ((R)1 - ct) * ((R)1 + ct);
                     const R sp2 = ((R)1 - mu) * ((R)1 + mu);
-                    const R sn = P<R>::sqrt_((st2 > (R)0 ? st2 : (R)0) * (sp2 > (R)0 ? sp2 : (R)0));
-                    mun = mu * ct + sn * P<R>::cos2pi(P<R>::uni(r1.y));
+                    if (WTD && o.use_g_S) {
+                        // Eq. 7 (a ratio of densities): the new cosine about the reference
+                        // direction from HG(g_S), the azimuth about the radius vector
+                        // uniform from the plane of the old direction and the radius
+                        // vector; weight = dust HG density at the scattering angle / HG(g_S)
+                        const R gS = (R)o.g_S;
+                        const R mup = hg_cos(gS, P<R>::uni(r1.x));
+                        mun = src == 0 ? -mup : mup;
+                        const R sn2 = ((R)1 - mun) * ((R)1 + mun);
+                        const R ct = mu * mun + P<R>::sqrt_((sp2 > (R)0 ? sp2 : (R)0) * (sn2 > (R)0 ? sn2 : (R)0)) *
+                                                    P<R>::cos2pi(P<R>::uni(r1.y));
+                        W *= hg_pdf((R)d.g, ct > (R)1 ? (R)1 : (ct < (R)-1 ? (R)-1 : ct)) * P<R>::rcp(hg_pdf(gS, mup));
+                    } else {
+                        const R ct = hg_cos((R)d.g, P<R>::uni(r1.x));
+                        const R st2 = ((R)1 - ct) * ((R)1 + ct);
+                        const R sn = P<R>::sqrt_((st2 > (R)0 ? st2 : (R)0) * (sp2 > (R)0 ? sp2 : (R)0));
+                        mun = mu * ct + sn * P<R>::cos2pi(P<R>::uni(r1.y));
+                    }
                     mun = mun > (R)1 ? (R)1 : (mun < (R)-1 ? (R)-1 : mun);
                 }
                 t = rr * mun;
                 b2 = r2 * ((R)1 - mun) * ((R)1 + mun);
             }
 
-            // both free paths are redrawn after every event (Eq. 1)
-            R tauA = P<R>::nlog(P<R>::uni(absorbing ? r1.w : r1.z));
-            R tauS = P<R>::nlog(P<R>::uni(absorbing ? r2b.x : r1.w));
+            // both free paths are redrawn after every event (Eq. 1), from
+            // k e^{-k tau} when scaled (Eq. 8)
+            R tauA = P<R>::nlog(P<R>::uni(absorbing ? r1.w : r1.z)) * inv_kA;
+            R tauS = P<R>::nlog(P<R>::uni(absorbing ? r2b.x : r1.w)) * inv_kS;
+            bool kw_new = kscale;
 
             // launch geometry and launch weights (Eqs. 2-3, Eq. 5, Eqs. 9-12)
             if (launching) {
@@ -486,17 +579,41 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
                     if (!(tau0 > (R)0)) {
                         // no matter on the ray: the package leaves untouched
                         if (src == 0) lc.esc0 += eps * (double)W; else lc.esc1 += eps * (double)W;
+                        if (sed) {
+                            atomicAdd(&sed[src * K + k], eps * (double)W);
+                            atomicAdd(&sed[2 * K + src * K + k], eps * (double)W);
+                        }
                         lc.escape++;
                         lc.direct++;
                         launching = false;
                         st = ST_DEAD;
                     } else {
                         const R pf = -P<R>::expm1_(-tau0);
-                        lc.ffi += eps * (double)W * (double)(((R)1) - pf);
-                        W *= pf;
-                        const R tau = -P<R>::log1p_(-P<R>::uni(r1.z) * pf);
+                        const double unforced = eps * (double)W * (double)(((R)1) - pf);
+                        lc.ffi += unforced;
+                        if (sed) {
+                            // the unforced fraction leaves unscattered at the launch frequency
+                            atomicAdd(&sed[src * K + k], unforced);
+                            atomicAdd(&sed[2 * K + src * K + k], unforced);
+                        }
+                        R tau;
+                        if (WTD && o.ffi == 2) {
+                            // Eqs. 10, 12 in absorption depth: the interaction point is
+                            // drawn in absorption depth tA < tau0 (1 - a); its extinction
+                            // depth is tA / (1 - a); weight = ratio of the densities of
+                            // the point in extinction depth
+                            const R a1 = (R)1 - d.alb;
+                            const R pA = -P<R>::expm1_(-tau0 * a1);
+                            const R tA = -P<R>::log1p_(-P<R>::uni(r1.z) * pA);
+                            tau = tA * P<R>::rcp(a1);
+                            W *= pA * P<R>::rcp(a1) * P<R>::exp_(tA - tau);
+                        } else {
+                            W *= pf;
+                            tau = -P<R>::log1p_(-P<R>::uni(r1.z) * pf);
+                        }
                         if (P<R>::uni(r1.w) < d.alb) { tauS = tau * d.alb; tauA = P<R>::inf(); }
                         else { tauA = tau * ((R)1 - d.alb); tauS = P<R>::inf(); }
+                        kw_new = false;
                     }
                 }
                 W0 = W;
@@ -512,6 +629,8 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
                 const R sS = tauS * d.inv_kS;
                 ev_abs = sA <= sS;
                 sig = ev_abs ? sA : sS;
+                sig0 = sig;
+                kw = kw_new;
                 st = ST_FLY;
             }
     };
@@ -560,6 +679,13 @@ __device__ __forceinline__ void flush_counters(const LaneCounters &lc, DevStats 
     }
 }
 
+// Add this workgroup's escaping spectrum (LDS) to the launch's (global).
+__device__ __forceinline__ void flush_sed(const double *s_sed, int n, double *sed) {
+    __syncthreads();
+    for (int j = threadIdx.x; j < n; j += blockDim.x)
+        if (s_sed[j] != 0.0) unsafeAtomicAdd(&sed[j], s_sed[j]);
+}
+
 template <typename R>
 __device__ __forceinline__ void single_model(const TraceParams &p, const typename P<R>::Shell *sh,
                                              ModelCtx<R> &mc, MethodOpts &o) {
@@ -581,9 +707,15 @@ __device__ __forceinline__ void single_model(const TraceParams &p, const typenam
     o.batch = p.batch;
     o.w_floor = p.w_floor;
     o.max_events = p.max_events;
+    o.use_g_E = p.use_g_E;
+    o.g_E = p.g_E;
+    o.use_g_S = p.use_g_S;
+    o.g_S = p.g_S;
+    o.k_A = p.k_A;
+    o.k_S = p.k_S;
 }
 
-template <bool AGG>
+template <bool AGG, bool WTD>
 __global__ __launch_bounds__(kBlockFP32) void ire_trace_f32(TraceParams p) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int nsh = p.n + p.cavity + kSentinels, K = p.K, n_t = p.n_t;
@@ -592,38 +724,52 @@ __global__ __launch_bounds__(kBlockFP32) void ire_trace_f32(TraceParams p) {
     float *s_cdf = reinterpret_cast<float *>(s_dust + K);
     float *s_G = s_cdf + 2 * K;
     float *s_D = s_G + n_t;
+    uint32_t *s_guide = reinterpret_cast<uint32_t *>(s_D + (size_t)n_t * K);
     for (int j = threadIdx.x; j < nsh; j += blockDim.x) s_sh[j] = p.shf[j];
     for (int j = threadIdx.x; j < K; j += blockDim.x) s_dust[j] = p.dustf[j];
     for (int j = threadIdx.x; j < 2 * K; j += blockDim.x) s_cdf[j] = p.cdff[j];
     for (int j = threadIdx.x; j < n_t; j += blockDim.x) s_G[j] = p.Gf[j];
     const int nd = n_t * K;
     for (int j = threadIdx.x; j < nd; j += blockDim.x) s_D[j] = p.Df[j];
+    const int ng = (int)(guide_bytes(n_t) / 4);
+    for (int j = threadIdx.x; j < ng; j += blockDim.x) s_guide[j] = reinterpret_cast<const uint32_t *>(p.guide)[j];
+    double *s_sed = reinterpret_cast<double *>(s_guide + ng);
+    for (int j = threadIdx.x; j < 4 * K; j += blockDim.x) s_sed[j] = 0.0;
     __syncthreads();
     ModelCtx<float> mc;
     MethodOpts o;
     single_model<float>(p, s_sh, mc, o);
     const long long gtid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     LaneCounters lc;
-    trace_model<float, AGG>(mc, o, s_dust, s_cdf, s_G, s_D, K, n_t, &p.stats->cursor, p.chunk,
-                                   p.max_lanes > 0 && gtid >= p.max_lanes, lc);
+    trace_model<float, AGG, WTD>(mc, o, s_dust, s_cdf, s_G, s_D, K, n_t, reinterpret_cast<const unsigned char *>(s_guide),
+                                 p.g_lg0, p.g_scale, &p.stats->cursor, p.chunk,
+                                 p.max_lanes > 0 && gtid >= p.max_lanes, lc, s_sed);
     flush_counters(lc, p.stats);
+    flush_sed(s_sed, 4 * K, p.sed);
 }
 
-template <bool AGG>
+template <bool AGG, bool WTD>
 __global__ __launch_bounds__(256) void ire_trace_f64(TraceParams p) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *s_sed = reinterpret_cast<double *>(smem);
+    for (int j = threadIdx.x; j < 4 * p.K; j += blockDim.x) s_sed[j] = 0.0;
+    __syncthreads();
     ModelCtx<double> mc;
     MethodOpts o;
     single_model<double>(p, p.shd, mc, o);
     const long long gtid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     LaneCounters lc;
-    trace_model<double, AGG>(mc, o, p.dustd, p.cdfd, p.Gd, p.Dd, p.K, p.n_t, &p.stats->cursor, p.chunk,
-                                p.max_lanes > 0 && gtid >= p.max_lanes, lc);
+    trace_model<double, AGG, WTD>(mc, o, p.dustd, p.cdfd, p.Gd, p.Dd, p.K, p.n_t, p.guide, p.g_lg0, p.g_scale,
+                                  &p.stats->cursor, p.chunk, p.max_lanes > 0 && gtid >= p.max_lanes, lc, s_sed);
     flush_counters(lc, p.stats);
+    flush_sed(s_sed, 4 * p.K, p.sed);
 }
 
-__global__ void ire_zero(double *A, int n, DevStats *st, int clear_counts) {
+__global__ void ire_zero(double *A, int n, DevStats *st, int clear_counts, double *sed, int n_sed) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     for (int j = tid; j < n * kAccStride; j += gridDim.x * blockDim.x) A[j] = 0.0;
+    if (clear_counts)
+        for (int j = tid; j < n_sed; j += gridDim.x * blockDim.x) sed[j] = 0.0;
     if (tid == 0) {
         st->cursor = 0;
         if (clear_counts) {
@@ -667,7 +813,7 @@ __global__ void ire_finalize(FinalizeParams p) {
 // next to the shared dust / G / re-emission tables, traces the range with all
 // its waves (package indices from an LDS cursor), and drains before the next.
 
-template <bool AGG>
+template <bool AGG, bool WTD>
 __global__ __launch_bounds__(kBlockFP32) void ire_trace_batch(BatchParams p) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ unsigned long long s_item;
@@ -678,11 +824,14 @@ __global__ __launch_bounds__(kBlockFP32) void ire_trace_batch(BatchParams p) {
     float *s_cdf = reinterpret_cast<float *>(s_dust + K);
     float *s_G = s_cdf + 2 * K;
     float *s_D = s_G + n_t;
+    uint32_t *s_guide = reinterpret_cast<uint32_t *>(s_D + (size_t)n_t * K);
     for (int j = threadIdx.x; j < K; j += blockDim.x) s_dust[j] = p.dustf[j];
     for (int j = threadIdx.x; j < 2 * K; j += blockDim.x) s_cdf[j] = p.cdff[j];
     for (int j = threadIdx.x; j < n_t; j += blockDim.x) s_G[j] = p.Gf[j];
     const int nd = n_t * K;
     for (int j = threadIdx.x; j < nd; j += blockDim.x) s_D[j] = p.Df[j];
+    const int ng = (int)(guide_bytes(n_t) / 4);
+    for (int j = threadIdx.x; j < ng; j += blockDim.x) s_guide[j] = reinterpret_cast<const uint32_t *>(p.guide)[j];
 
     MethodOpts o;
     o.k_bg = p.k_bg;
@@ -691,6 +840,12 @@ __global__ __launch_bounds__(kBlockFP32) void ire_trace_batch(BatchParams p) {
     o.batch = p.batch;
     o.w_floor = p.w_floor;
     o.max_events = p.max_events;
+    o.use_g_E = p.use_g_E;
+    o.g_E = p.g_E;
+    o.use_g_S = p.use_g_S;
+    o.g_S = p.g_S;
+    o.k_A = p.k_A;
+    o.k_S = p.k_S;
     LaneCounters lc;
     for (;;) {
         __syncthreads();  // every wave has finished the previous item: the shell slot is free
@@ -719,7 +874,9 @@ __global__ __launch_bounds__(kBlockFP32) void ire_trace_batch(BatchParams p) {
         mc.pid0[0] = item.first;
         mc.pid0[1] = item.first;
         mc.seed = bm.seed;
-        trace_model<float, AGG>(mc, o, s_dust, s_cdf, s_G, s_D, K, n_t, &s_cursor, 64ull, false, lc);
+        trace_model<float, AGG, WTD>(mc, o, s_dust, s_cdf, s_G, s_D, K, n_t,
+                                     reinterpret_cast<const unsigned char *>(s_guide), p.g_lg0, p.g_scale, &s_cursor,
+                                     64ull, false, lc, nullptr);
     }
     flush_counters(lc, p.stats);
 }
@@ -761,42 +918,61 @@ __global__ void ire_finalize_batch(BatchFinalizeParams p) {
 
 size_t trace_lds_bytes(int n_table, int K, int n_t) {
     return (size_t)n_table * sizeof(ShellF) + (size_t)K * sizeof(DustF) + (size_t)2 * K * sizeof(float) +
-           (size_t)n_t * sizeof(float) + (size_t)n_t * K * sizeof(float);
+           (size_t)n_t * sizeof(float) + (size_t)n_t * K * sizeof(float) + guide_bytes(n_t) + sed_lds_bytes(K);
 }
 
-static const void *f32_kernel(int aggregate) {
-    return aggregate ? reinterpret_cast<const void *>(&ire_trace_f32<true>)
-                     : reinterpret_cast<const void *>(&ire_trace_f32<false>);
+size_t sed_lds_bytes(int K) { return (size_t)4 * K * sizeof(double); }
+
+static const void *f32_kernel(int aggregate, bool wtd) {
+    if (wtd) return aggregate ? reinterpret_cast<const void *>(&ire_trace_f32<true, true>)
+                              : reinterpret_cast<const void *>(&ire_trace_f32<false, true>);
+    return aggregate ? reinterpret_cast<const void *>(&ire_trace_f32<true, false>)
+                     : reinterpret_cast<const void *>(&ire_trace_f32<false, false>);
 }
 
-static const void *batch_kernel(int aggregate) {
-    return aggregate ? reinterpret_cast<const void *>(&ire_trace_batch<true>)
-                     : reinterpret_cast<const void *>(&ire_trace_batch<false>);
+static const void *batch_kernel(int aggregate, bool wtd) {
+    if (wtd) return aggregate ? reinterpret_cast<const void *>(&ire_trace_batch<true, true>)
+                              : reinterpret_cast<const void *>(&ire_trace_batch<false, true>);
+    return aggregate ? reinterpret_cast<const void *>(&ire_trace_batch<true, false>)
+                     : reinterpret_cast<const void *>(&ire_trace_batch<false, false>);
+}
+
+static const void *f64_kernel(int aggregate, bool wtd) {
+    if (wtd) return aggregate ? reinterpret_cast<const void *>(&ire_trace_f64<true, true>)
+                              : reinterpret_cast<const void *>(&ire_trace_f64<false, true>);
+    return aggregate ? reinterpret_cast<const void *>(&ire_trace_f64<true, false>)
+                     : reinterpret_cast<const void *>(&ire_trace_f64<false, false>);
+}
+
+// The weighted-sampling instantiation is used only when an option needs it,
+// so that the default path keeps its register budget.
+template <typename Params>
+static bool weighted(const Params &p) {
+    return p.use_g_E || p.use_g_S || p.k_A != 1.0 || p.k_S != 1.0 || p.ffi == 2;
 }
 
 hipError_t trace_configure(int fp64, int aggregate, size_t lds) {
     if (fp64) return hipSuccess;
-    return hipFuncSetAttribute(f32_kernel(aggregate), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute(f32_kernel(aggregate, false), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(f32_kernel(aggregate, true), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 hipError_t launch_trace(const TraceParams &p, int fp64, int aggregate, int grid, int block, size_t lds,
                         hipStream_t s) {
-    if (fp64) {
-        if (aggregate) hipLaunchKernelGGL(ire_trace_f64<true>, dim3(grid), dim3(block), 0, s, p);
-        else hipLaunchKernelGGL(ire_trace_f64<false>, dim3(grid), dim3(block), 0, s, p);
-        return hipGetLastError();
-    }
     TraceParams q = p;
     void *args[] = {&q};
-    return hipLaunchKernel(f32_kernel(aggregate), dim3(grid), dim3(block), args, lds, s);
+    if (fp64) return hipLaunchKernel(f64_kernel(aggregate, weighted(p)), dim3(grid), dim3(block), args,
+                                     sed_lds_bytes(p.K), s);
+    return hipLaunchKernel(f32_kernel(aggregate, weighted(p)), dim3(grid), dim3(block), args, lds, s);
 }
 
-hipError_t launch_zero(double *A, int n, DevStats *st, int clear_counts, hipStream_t s) {
+hipError_t launch_zero(double *A, int n, DevStats *st, int clear_counts, double *sed, int n_sed, hipStream_t s) {
     if (A) {
         int blocks = (n * kAccStride + 255) / 256;
         if (blocks < 1) blocks = 1;
         if (blocks > 1024) blocks = 1024;
-        hipLaunchKernelGGL(ire_zero, dim3(blocks), dim3(256), 0, s, A, n, st, clear_counts);
+        hipLaunchKernelGGL(ire_zero, dim3(blocks), dim3(256), 0, s, A, n, st, clear_counts, sed, n_sed);
     } else {
         hipLaunchKernelGGL(ire_cursor_reset, dim3(1), dim3(64), 0, s, st);
     }
@@ -813,13 +989,15 @@ hipError_t launch_finalize(const FinalizeParams &p, hipStream_t s) {
 int trace_block_fp32() { return kBlockFP32; }
 
 hipError_t batch_configure(int aggregate, size_t lds) {
-    return hipFuncSetAttribute(batch_kernel(aggregate), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute(batch_kernel(aggregate, false), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(batch_kernel(aggregate, true), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 hipError_t launch_trace_batch(const BatchParams &p, int aggregate, int grid, size_t lds, hipStream_t s) {
     BatchParams q = p;
     void *args[] = {&q};
-    return hipLaunchKernel(batch_kernel(aggregate), dim3(grid), dim3(kBlockFP32), args, lds, s);
+    return hipLaunchKernel(batch_kernel(aggregate, weighted(p)), dim3(grid), dim3(kBlockFP32), args, lds, s);
 }
 
 hipError_t launch_zero_batch(double *A, size_t n_shells, DevStats *st, hipStream_t s) {

@@ -174,15 +174,15 @@ int sur_create(int hip_device, int32_t members, int32_t width, int32_t depth, ui
         sur_destroy(s);
         return IRE_E_DEVICE;
     }
-    // He-uniform weights (fan-in: the 6 real inputs for the first layer), zero biases
+    // He-uniform weights (fan-in: the 6 real inputs and the derived one for the first layer), zero biases
     std::vector<float> p(M * s->p_stride, 0.0f);
     for (size_t m = 0; m < M; ++m) {
         uint64_t st = seed * 0x100000001B3ull + m + 1;
         auto uni = [&]() { return (float)((splitmix(st) >> 11) * 0x1p-53); };
         float *q = p.data() + m * s->p_stride;
-        const float a0 = std::sqrt(6.0f / sur::kFeatures);
+        const float a0 = std::sqrt(6.0f / sur::kNetInputs);
         for (size_t o = 0; o < W; ++o)
-            for (int i = 0; i < sur::kFeatures; ++i) q[o * sur::kIn + i] = a0 * (2.0f * uni() - 1.0f);
+            for (int i = 0; i < sur::kNetInputs; ++i) q[o * sur::kIn + i] = a0 * (2.0f * uni() - 1.0f);
         const float a = std::sqrt(6.0f / (float)W);
         for (size_t j = W * sur::kIn; j < s->w_stride; ++j) q[j] = a * (2.0f * uni() - 1.0f);
         const float ao = std::sqrt(3.0f / (float)W);
@@ -249,10 +249,10 @@ int sur_set_params(sur_net *s, const float *params) {
     if (!finite_f(params, n)) return s->fail(IRE_E_INVALID, "non-finite parameters");
     if (hipSetDevice(s->device) != hipSuccess) return s->fail(IRE_E_DEVICE, "hipSetDevice");
     std::vector<float> p(params, params + n);
-    // inputs beyond the real features carry no weight
+    // the padding inputs carry no weight
     for (int m = 0; m < s->members; ++m)
         for (int o = 0; o < sur::kWidth; ++o)
-            for (int i = sur::kFeatures; i < sur::kIn; ++i) p[(size_t)m * s->p_stride + (size_t)o * sur::kIn + i] = 0.0f;
+            for (int i = sur::kNetInputs; i < sur::kIn; ++i) p[(size_t)m * s->p_stride + (size_t)o * sur::kIn + i] = 0.0f;
     return upload_params(s, p);
 }
 

@@ -8,10 +8,12 @@ namespace sur {
 
 constexpr int kWidth = 256;    // hidden width
 constexpr int kFeatures = 6;   // cloud/shell parameters per row
+constexpr int kLogRadius = kFeatures;  // one input derived from the six: log10(max(r/R_out, 1e-4)) + 1.5
+constexpr int kNetInputs = kFeatures + 1;
 constexpr int kIn = 32;        // inputs padded to the MFMA k granularity
 
 // Parameter layout per ensemble member (FP32 master, flat):
-//   [0, kWidth*kIn)                 W_0 (row-major [out][in], inputs beyond kFeatures stay zero)
+//   [0, kWidth*kIn)                 W_0 (row-major [out][in], inputs beyond kNetInputs stay zero)
 //   (depth-1) blocks of kWidth^2    W_1 .. W_{depth-1}
 //   off_b:    depth*kWidth          hidden biases
 //   off_wout: kWidth                output weights

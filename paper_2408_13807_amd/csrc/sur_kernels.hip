@@ -40,10 +40,9 @@ __device__ __forceinline__ f32x16 mfma(const bf16x8 &a, const bf16x8 &b, const f
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
-// The network sees one input derived from the six: log10 of the relative
-// radius (floored at 1e-4) shifted by 1.5, which spreads the inner shells of
-// log-spaced grids that r / R_out alone packs near zero.
-constexpr int kLogRadius = kFeatures;
+// The network sees one input derived from the six (kLogRadius): log10 of the
+// relative radius (floored at 1e-4) shifted by 1.5, which spreads the inner
+// shells of log-spaced grids that r / R_out alone packs near zero.
 __device__ __forceinline__ float log_radius_input(float r) { return log10f(fmaxf(r, 1e-4f)) + 1.5f; }
 
 // Normalised inputs of rows [row0, row0 + kR) into the LDS input tile (zero padded).

@@ -26,7 +26,7 @@ IRE_FP64 = 1
 EXPORTS = ("ire_default_options", "ire_create", "ire_destroy", "ire_set_shells", "ire_set_dust",
            "ire_set_temperature_grid", "ire_set_external_field", "ire_set_point_source",
            "ire_set_options", "ire_run", "ire_begin", "ire_advance", "ire_reset", "ire_sync",
-           "ire_get_results", "ire_get_stats", "ire_get_results_dev", "ire_last_error", "ire_planck",
+           "ire_get_results", "ire_get_stats", "ire_get_results_dev", "ire_get_sed", "ire_last_error", "ire_planck",
            "ire_batch_default_options", "ire_batch_create", "ire_batch_destroy", "ire_batch_set_dust",
            "ire_batch_set_temperature_grid", "ire_batch_set_sources", "ire_batch_set_models",
            "ire_batch_set_options", "ire_batch_run", "ire_batch_get", "ire_batch_autotune",
@@ -38,7 +38,9 @@ IRE_SRC_POINT = 1
 class Options(ct.Structure):
     _fields_ = [("k_bg", ct.c_double), ("ffi", ct.c_int32), ("w_floor", ct.c_double),
                 ("max_events", ct.c_uint64), ("stepping", ct.c_int32), ("max_lanes", ct.c_int32),
-                ("reemit_uniform", ct.c_int32), ("aggregate", ct.c_int32), ("batch", ct.c_int32)]
+                ("reemit_uniform", ct.c_int32), ("aggregate", ct.c_int32), ("batch", ct.c_int32),
+                ("use_g_E", ct.c_int32), ("g_E", ct.c_double), ("use_g_S", ct.c_int32), ("g_S", ct.c_double),
+                ("k_A", ct.c_double), ("k_S", ct.c_double)]
 
 
 class Stats(ct.Structure):
@@ -63,7 +65,9 @@ _MODEL_DESC_DTYPE = np.dtype({"names": ["n_shells", "source", "scale", "n_packag
 class BatchOptions(ct.Structure):
     _fields_ = [("k_bg", ct.c_double), ("ffi", ct.c_int32), ("w_floor", ct.c_double),
                 ("max_events", ct.c_uint64), ("reemit_uniform", ct.c_int32), ("aggregate", ct.c_int32),
-                ("batch", ct.c_int32), ("item_packages", ct.c_uint64), ("use_graph", ct.c_int32)]
+                ("batch", ct.c_int32), ("item_packages", ct.c_uint64), ("use_graph", ct.c_int32),
+                ("use_g_E", ct.c_int32), ("g_E", ct.c_double), ("use_g_S", ct.c_int32), ("g_S", ct.c_double),
+                ("k_A", ct.c_double), ("k_S", ct.c_double)]
 
 
 class BatchStats(ct.Structure):
@@ -113,6 +117,7 @@ _lib.ire_sync.argtypes = [_H]
 _lib.ire_get_results.argtypes = [_H, _DP, _DP, ct.POINTER(Stats)]
 _lib.ire_get_stats.argtypes = [_H, ct.POINTER(Stats)]
 _lib.ire_get_results_dev.argtypes = [_H, ct.c_void_p, ct.c_void_p, ct.c_void_p]
+_lib.ire_get_sed.argtypes = [_H, _DP, _DP]
 _lib.ire_last_error.argtypes = [_H]
 _lib.ire_last_error.restype = ct.c_char_p
 _lib.ire_planck.argtypes = [ct.c_int32, _DP, ct.c_double, _DP]
@@ -178,9 +183,10 @@ class IREModel:
             raise IREError(rc, f"ire_create(device={device}) failed")
         self._h = h
         self.n = 0
+        self.K = 0
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.ire_destroy(self._h)
             self._h = None
 
@@ -206,6 +212,7 @@ class IREModel:
     def set_dust(self, nu, kabs, albedo, g):
         a = [_arr(x) for x in (nu, kabs, albedo, g)]
         self._check(_lib.ire_set_dust(self._h, len(a[0][0]), *[p for _, p in a]))
+        self.K = len(a[0][0])
 
     def set_temperature_grid(self, t_min: float, t_max: float, n_t: int):
         self._check(_lib.ire_set_temperature_grid(self._h, float(t_min), float(t_max), int(n_t)))
@@ -265,6 +272,13 @@ class IREModel:
         out["escaped"] = list(st.escaped)
         return out
 
+    def sed(self) -> dict:
+        """Escaping spectrum per source and frequency: total and unscattered, [2, K] each."""
+        K = self.K
+        tot, direct = np.zeros(2 * K), np.zeros(2 * K)
+        self._check(_lib.ire_get_sed(self._h, tot.ctypes.data_as(_DP), direct.ctypes.data_as(_DP)))
+        return dict(sed=tot.reshape(2, K), sed_direct=direct.reshape(2, K))
+
     def results_dev(self, absorbed_ptr: int | None, T_ptr: int | None, stream=None):
         self._check(_lib.ire_get_results_dev(self._h, absorbed_ptr, T_ptr, _stream_ptr(stream)))
 
@@ -276,7 +290,9 @@ def run_model(model: dict, n_ext: int = 0, n_ps: int = 0, seed: int = 1, device:
         m.set_model(model)
         m.set_options(**opts)
         m.run(n_ext, n_ps, seed, stream)
-        return m.results(allow_limit=allow_limit)
+        r = m.results(allow_limit=allow_limit)
+        r.update(m.sed())
+        return r
 
 
 def default_batch_options(**kw) -> BatchOptions:

@@ -1,0 +1,109 @@
+"""Noise of the temperature estimates under weighted sampling, on the synthetic
+clouds: the studies of Sect. 3.2 (Figs. 5 and 6: one weighting parameter of
+Table 1 at a time; Fig. 7: default, fixed k_A and FFI against the optical
+depth).
+
+For every setting, R independent GPU runs (seeds 1..R) of the same cloud give
+the relative scatter std(T)/mean(T) at the surface shell, the shell holding
+half the outer radius and the innermost shell, and the tracer's mean duration.
+
+    python -m paper_2408_13807_amd.noise_study [--packages N] [--runs R] [--out FILE]
+
+prints one JSON line per setting (and writes them to FILE).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+
+import numpy as np
+
+from paper_2408_13807_amd import ire, workloads as wl
+
+# one parameter of Table 1 at a time (the unweighted value is in every list)
+SCANS = {
+    "k_bg": [0.1, 0.2, 0.3, 0.4, 0.5, 0.7],
+    "g_E": [-0.5, -0.25, 0.0, 0.25, 0.5],
+    "g_S": [-0.5, -0.25, 0.0, 0.25, 0.5],
+    "k_A": [0.5, 0.75, 1.0, 1.5, 2.0, 2.5],
+    "k_S": [0.5, 0.75, 1.0, 1.5, 2.0],
+}
+
+
+def options(key: str, value: float) -> dict:
+    if key == "g_E":
+        return dict(use_g_E=1, g_E=value)
+    if key == "g_S":
+        return dict(use_g_S=1, g_S=value)
+    return {key: value}
+
+
+def clouds() -> dict:
+    return {
+        "external_tauV10": (wl.external_sphere(n=101, tau_V=10.0), "n_ext"),
+        "external_tauV100": (wl.external_sphere(n=101, tau_V=100.0), "n_ext"),
+        "central_tauV10": (wl.central_source(n=100, tau_V=10.0), "n_ps"),
+        "central_tauV100": (wl.central_source(n=100, tau_V=100.0), "n_ps"),
+    }
+
+
+def probe_shells(r_edges: np.ndarray) -> dict:
+    rm = 0.5 * (r_edges[1:] + r_edges[:-1])
+    return {"surface": len(rm) - 1, "half_radius": int(np.searchsorted(r_edges, 0.5 * r_edges[-1]) - 1),
+            "centre": 0}
+
+
+def noise(model: dict, key: str, n_pkg: int, runs: int, opts: dict) -> dict:
+    T, ms = [], []
+    with ire.IREModel(0) as h:
+        h.set_model(model)
+        h.set_options(**opts)
+        for s in range(1, runs + 1):
+            h.run(seed=s, **{key: n_pkg})
+            r = h.results(allow_limit=True)
+            T.append(r["T"])
+            ms.append(r["stats"]["ms_trace"])
+    T = np.array(T)
+    rel = T.std(axis=0, ddof=1) / T.mean(axis=0)
+    out = {name: float(rel[i]) for name, i in probe_shells(model["r_edges"]).items()}
+    out["ms_trace"] = float(np.mean(ms))
+    return out
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--packages", type=float, default=1e7)
+    ap.add_argument("--runs", type=int, default=8)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args(argv)
+    n_pkg = int(a.packages)
+    lines = []
+
+    def emit(d):
+        print(json.dumps(d), flush=True)
+        lines.append(d)
+
+    for cname, (model, key) in clouds().items():
+        for param, values in SCANS.items():
+            if param == "k_bg" and key == "n_ps":
+                continue                       # background weighting has no meaning for a point source
+            for v in values:
+                emit(dict(study="one_parameter", cloud=cname, param=param, value=v,
+                          **noise(model, key, n_pkg, a.runs, options(param, v))))
+    # default, fixed k_A = 2.5 and FFI against the optical depth (externally heated)
+    for tau in (0.1, 0.3, 1.0, 3.0, 10.0):
+        model = wl.external_sphere(n=101, tau_V=tau)
+        for name, opts in (("default", {}), ("k_A=2.5", dict(k_A=2.5)), ("FFI", dict(ffi=1)),
+                           ("FFI absorption depth", dict(ffi=2))):
+            emit(dict(study="optical_depth", tau_V=tau, method=name,
+                      **noise(model, "n_ext", n_pkg, a.runs, opts)))
+    if a.out:
+        with open(a.out, "w") as f:
+            for d in lines:
+                f.write(json.dumps(d) + "\n")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -12,6 +12,9 @@
     python -m paper_2408_13807_amd.profiling copy [MiB]
         one device-to-device copy of MiB (default 1024) MiB: the reference
         dispatch that scales FETCH_SIZE / WRITE_SIZE into bytes
+    python -m paper_2408_13807_amd.profiling sur-predict [rows]
+        surrogate ensemble prediction (5 members, 4 x 256) of `rows` (default
+        2.1e7) device-resident rows, three launches: the MFMA kernel to profile
 """
 from __future__ import annotations
 
@@ -111,6 +114,26 @@ def main(argv: list[str]) -> int:
         print(json.dumps(valu_fit(argv[1], cases), indent=1))
     elif cmd == "summary":
         print(summary(argv[1:]))
+    elif cmd == "sur-predict":
+        import time
+        import torch
+        from paper_2408_13807_amd import surrogate
+        n = int(float(argv[1])) if len(argv) > 1 else 21_000_000
+        rng = np.random.default_rng(0)
+        net = surrogate.SurNet(members=5, depth=4, seed=1)
+        net.set_normalization(np.zeros(6), np.ones(6), 1.3, 0.3)
+        X = torch.from_numpy(rng.normal(size=(n, 6)).astype(np.float32)).cuda()
+        mean = torch.empty(n, device="cuda")
+        spread = torch.empty(n, device="cuda")
+        torch.cuda.synchronize()
+        for _ in range(3):
+            t0 = time.perf_counter()
+            net.predict_dev(X.data_ptr(), n, mean.data_ptr(), spread.data_ptr())
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            flop = 2.0 * n * 5 * (32 * 256 + 3 * 256 * 256 + 256)
+            print(json.dumps({"rows": n, "s": dt, "rows_per_s": n / dt, "tflops": flop / dt / 1e12}), flush=True)
+        net.close()
     elif cmd == "copy":
         import torch
         n = (int(argv[1]) if len(argv) > 1 else 1024) << 18   # float32 elements

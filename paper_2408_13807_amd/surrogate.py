@@ -165,9 +165,10 @@ class SurNet:
 
 
 def ire_profiles(params: dict, models, package_scale: float = 1.0, chunk: int = 16384, device: int = 0,
-                 options: dict | None = None) -> dict:
+                 options: dict | None = None, progress=None) -> dict:
     """Per-shell temperatures of study models from batched IRE launches of at
-    most `chunk` models each; T of all models end to end with row offsets."""
+    most `chunk` models each; T of all models end to end with row offsets.
+    `progress(done, total, seconds)` is called after every launch."""
     models = np.asarray(models, np.int64)
     T, A, secs, pk = [], [], 0.0, 0
     for c0 in range(0, len(models), chunk):
@@ -182,6 +183,8 @@ def ire_profiles(params: dict, models, package_scale: float = 1.0, chunk: int = 
         T.append(r["T"])
         A.append(r["A"])
         b.close()
+        if progress:
+            progress(min(c0 + chunk, len(models)), len(models), secs)
     n = params["n"][models].astype(np.int64)
     row_off = np.zeros(len(models) + 1, np.int64)
     np.cumsum(n, out=row_off[1:])
@@ -238,11 +241,18 @@ def predict_with_fallback(net: SurNet, params: dict, models, threshold: float = 
                 seconds_predict=t1 - t0, seconds_fallback=ire_s, seconds_total=t2 - t0)
 
 
-def model_errors(T: np.ndarray, T_ref: np.ndarray, row_off: np.ndarray) -> np.ndarray:
-    """Mean relative temperature error |T - T_ref| / T_ref over the shells of each model."""
+def model_errors(T: np.ndarray, T_ref: np.ndarray, row_off: np.ndarray, stat: str = "median") -> np.ndarray:
+    """Per-model relative temperature error |T - T_ref| / T_ref over the shells
+    of each model: the median over shells (default; robust to the few shells
+    whose reference is itself Monte Carlo noise) or the mean."""
     d = np.abs(T - T_ref) / T_ref
     n = np.diff(row_off)
     out = np.zeros(len(n))
-    nz = n > 0
-    out[nz] = np.add.reduceat(d, row_off[:-1][nz]) / n[nz]
+    if stat == "mean":
+        nz = n > 0
+        out[nz] = np.add.reduceat(d, row_off[:-1][nz]) / n[nz]
+        return out
+    for j in range(len(n)):
+        if n[j]:
+            out[j] = np.median(d[row_off[j]:row_off[j + 1]])
     return out

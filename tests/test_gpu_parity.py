@@ -62,6 +62,11 @@ SERIAL_CASES = [
     ("gray_cavity_mixed", lambda: dict(wl.gray_model(10, 2.0, external=False, r_in=0.1 * wl.R_OUT),
                                        J=1e-13 * wl.blackbody(wl.frequency_grid(8, 1e12, 1e15), 8000.0)),
      dict(n_ext=500, n_ps=500), {}),
+    # weighted sampling (Table 1) and FFI in absorption depth
+    ("ext50_gE_gS", wl.cfg_external_small, dict(n_ext=2000), dict(use_g_E=1, g_E=0.4, use_g_S=1, g_S=0.5)),
+    ("ext101_kA_kS", wl.cfg_external_large, dict(n_ext=600), dict(k_A=1.8, k_S=0.6)),
+    ("central200_gE_kA", wl.cfg_central, dict(n_ps=150), dict(use_g_E=1, g_E=-0.3, k_A=0.7)),
+    ("ext50_ffi_abs", wl.cfg_external_small, dict(n_ext=2000), dict(ffi=2)),
 ]
 
 
@@ -70,10 +75,13 @@ def test_serial_fp64_matches_oracle_elementwise(ire, name, factory, npk, opts):
     m = factory()
     print(f"case {name} {npk} {opts}", flush=True)
     g = ire.run_model(m, seed=11, stepping=ire.IRE_FP64, max_lanes=1, **npk, **opts)
-    o = oracle.run(m, seed=11, **npk, **opts)
+    o = oracle.run(m, seed=11, sed=True, **npk, **opts)
     assert counts(g["stats"]) == {k: o["stats"][k] for k in counts(g["stats"])}
     np.testing.assert_allclose(g["A"], o["A"], rtol=1e-9, atol=0)
     np.testing.assert_allclose(g["T"], o["T"], rtol=1e-9)
+    # escaping spectrum per source and frequency, and its unscattered part
+    np.testing.assert_allclose(g["sed"], o["sed"], rtol=1e-9, atol=1e-12 * o["sed"].max())
+    np.testing.assert_allclose(g["sed_direct"], o["sed_direct"], rtol=1e-9, atol=1e-12 * o["sed"].max())
     for k in ("escaped", "ffi_escaped", "terminated"):
         np.testing.assert_allclose(g["stats"][k], o["stats"][k], rtol=1e-9, atol=0)
 
@@ -117,6 +125,19 @@ def test_parallel_central_ensemble(ire):
     assert_ensemble_parity(r["T"], g, name="central200 1e6")
 
 
+@pytest.mark.parametrize("opts", [dict(use_g_E=1, g_E=0.4, use_g_S=1, g_S=0.5), dict(k_A=1.5, k_S=0.7),
+                                  dict(ffi=2, k_bg=0.3)])
+def test_parallel_weighted_against_oracle_ensemble(ire, opts):
+    # the FP32 parallel path with weighted sampling against the oracle's
+    # ensemble with the same weights (16 seeds x 1e5 packages)
+    m = wl.cfg_external_small()
+    e = oracle.ensemble(m, n_ext=100_000, seeds=range(1, 17), **opts)
+    r = ire.run_model(m, n_ext=100_000, seed=107, **opts)
+    ok, f = mc_stats.compare_runs(r["T"], e["T"], e["A"], name=f"ext50 {opts}")
+    print(f"ext50 weighted {opts}: {f * 100:.1f}% of shells within max(1%, 3 sigma)")
+    assert ok
+
+
 @pytest.mark.parametrize("name,factory,npk,gold", [
     ("ext101_1e8", wl.cfg_external_large, dict(n_ext=100_000_000), "ext101_tau10_1e7"),
     ("central200_1e8", wl.cfg_central, dict(n_ps=100_000_000), "central200_tau100_1e7"),
@@ -138,6 +159,22 @@ def test_schedule_options_do_not_change_results(ire, opts):
     g = golden("ext50_tau1_1e5")
     r = ire.run_model(wl.cfg_external_small(), n_ext=100_000, seed=106, **opts)
     assert_ensemble_parity(r["T"], g, name=f"ext50 {opts}")
+
+
+def test_parallel_sed_against_oracle_ensemble(ire):
+    # the escaping spectrum of the parallel FP32 path against the oracle's
+    # 16-seed ensemble, per frequency where the oracle's spectrum is well sampled
+    m = dict(wl.cfg_external_small(), L_ps=wl.LSUN, S=wl.blackbody(wl.frequency_grid(), 5000.0))
+    runs = [oracle.run(m, n_ext=50_000, n_ps=50_000, seed=s, sed=True) for s in range(1, 17)]
+    e = np.stack([r["sed"] for r in runs])
+    mean, sd = e.mean(0), e.std(0, ddof=1)
+    r = ire.run_model(m, n_ext=50_000, n_ps=50_000, seed=99)
+    well = mean > 50 * sd / 16 ** 0.5
+    z = np.abs(r["sed"] - mean)[well] / (sd[well] * np.sqrt(1 + 1 / 16))
+    assert np.mean(z < 3) >= 0.95 and z.max() < 6, (np.mean(z < 3), z.max())
+    tot = r["sed"].sum()
+    s = r["stats"]
+    assert abs(tot / (sum(s["escaped"]) + s["ffi_escaped"]) - 1) < 1e-9
 
 
 def test_energy_conservation_and_counts(ire):
@@ -184,8 +221,18 @@ def test_invalid_arguments_rejected(ire):
         with pytest.raises(ire.IREError) as e:
             h.run(0, 100, 1)           # no point source set
         assert e.value.code == ire.IRE_E_STATE
+        for bad in (dict(k_bg=0.0), dict(k_A=0.0), dict(k_S=float("inf")), dict(use_g_E=1, g_E=1.0),
+                    dict(use_g_S=2), dict(ffi=3)):
+            with pytest.raises(ire.IREError) as e:
+                h.set_options(**bad)
+            assert e.value.code == ire.IRE_E_INVALID, bad
+        K = 256                        # guide tables index at most 255 frequencies
+        nu = np.geomspace(1e12, 1e15, K)
         with pytest.raises(ire.IREError) as e:
-            h.set_options(k_bg=0.0)
+            h.set_dust(nu, np.ones(K), np.zeros(K), np.zeros(K))
+        assert e.value.code == ire.IRE_E_INVALID
+        with pytest.raises(ire.IREError) as e:
+            h.set_temperature_grid(3.0, 1600.0, 70000)
         assert e.value.code == ire.IRE_E_INVALID
         h.begin(100, 0, 1)
         with pytest.raises(ire.IREError) as e:
