@@ -27,9 +27,14 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 # VALU instructions one lane executes per event on the FP32 tracer's paths
-# (least-squares fit of SQ_INSTS_VALU over one-lane runs of several clouds;
-# the fit and the command that produced it are kept under profiles/).
-VALU_PER_EVENT = {"cross": 34.0, "launch": 330.0, "scat": 250.0, "abs": 520.0}
+# (least-squares fit of SQ_INSTS_VALU over one-lane runs of six clouds;
+# profiles/valu_fit_one_lane_clouds.md holds the fit and its command).
+VALU_PER_EVENT = {"cross": 23.71, "launch": 356.06, "scat": 270.40, "abs": 377.08}
+
+# HBM bytes per tracer launch from FETCH_SIZE and WRITE_SIZE, scaled by a
+# plain 1 GiB copy (profiles/ire_trace_f32_ext101_tauV10_1e8.md); valid for
+# the tracer as profiled and set to None whenever the kernel changes.
+TRAFFIC_BYTES = {"ext101_tauV10_1e8": 2.009e9}
 
 # MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = VALU lane-instruction issue peak
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
@@ -343,10 +348,10 @@ def main() -> int:
         "T_center_K": float(host_res["T"][0]),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
                      "unit": "TOP/s (VALU lane-instructions)", "frac": achieved / VALU_PEAK_TOPS,
-                     "traffic": None},
+                     "traffic": TRAFFIC_BYTES.get(args.workload)},
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(model, key, 500_000, 16, "same cloud, same package budget per seed")
+        line["cpu_baseline"] = cpu_baseline(model, key, 1_500_000, 16, "same cloud")
     h.close()
     print(json.dumps(line), flush=True)
     return 0

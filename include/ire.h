@@ -147,7 +147,9 @@ int ire_get_stats(ire_model *m, ire_stats *stats);
  * source and frequency, sed[2][K] (external, then point source; the unforced
  * fraction of FFI packages included at their launch frequency), and the part
  * that left without any scattering or absorption, sed_direct[2][K].  Either
- * pointer may be NULL. */
+ * pointer may be NULL.  With both sources, which source's packages carry the
+ * re-emitted light depends on the order of the absorptions (packages of both
+ * sources run at once); the sum over sources and the unscattered parts do not. */
 int ire_get_sed(ire_model *m, double *sed, double *sed_direct);
 
 /* Device-pointer variant: writes absorbed[n] and T[n] into caller device

@@ -80,7 +80,7 @@ def summary(dbs: list[str]) -> str:
         except sqlite3.Error:
             rows = []
         if rows:
-            lines.append("| kernel | calls | total (us) | average (us) | % |")
+            lines.append("| kernel | calls | total (ms) | average (ms) | % |")
             lines.append("|---|---|---|---|---|")
             for name, calls, tot, avg, pct in rows:
                 lines.append(f"| `{name[:90]}` | {calls} | {tot / 1e3:.1f} | {avg / 1e3:.1f} | {pct:.2f} |")

