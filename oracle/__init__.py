@@ -43,7 +43,8 @@ class Options(ct.Structure):
                 ("max_events", ct.c_uint64), ("table_mode", ct.c_int32),
                 ("acc_bits", ct.c_int32), ("n_batches", ct.c_int32),
                 ("reemit_uniform", ct.c_int32), ("use_g_E", ct.c_int32), ("g_E", ct.c_double),
-                ("use_g_S", ct.c_int32), ("g_S", ct.c_double), ("k_A", ct.c_double), ("k_S", ct.c_double)]
+                ("use_g_S", ct.c_int32), ("g_S", ct.c_double), ("k_A", ct.c_double), ("k_S", ct.c_double),
+                ("k_A_rho", ct.c_int32), ("k_A_lowest", ct.c_double), ("k_A_highest", ct.c_double)]
 
 
 class Stats(ct.Structure):

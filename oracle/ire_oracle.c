@@ -145,6 +145,8 @@ typedef struct {
     double *rho;              /* nsh */
     double *M;                /* nsh masses */
     double *w, *kA, *kS, *g, *alb;
+    double *kAsh;             /* nsh: absorption free-path scaling per shell (Eq. 8, constant or k_A(rho)) */
+    int kscale;               /* any free-path scaling */
     double *cdf[2];
     double L[2], eps[2];
     double *Tg, *lnT, *G, *lnG, *D;   /* tables (n_t and n_t*K) */
@@ -250,7 +252,7 @@ static int validate(const or_model *m) {
 }
 
 static void state_free(ostate *s) {
-    free(s->R); free(s->rho); free(s->M); free(s->w); free(s->kA); free(s->kS);
+    free(s->R); free(s->rho); free(s->M); free(s->w); free(s->kA); free(s->kS); free(s->kAsh);
     free(s->g); free(s->alb); free(s->cdf[0]); free(s->cdf[1]); free(s->Tg); free(s->lnT);
     free(s->G); free(s->lnG); free(s->D); free(s->q);
 }
@@ -260,6 +262,10 @@ static int state_init(ostate *s, const or_model *m, const or_options *o) {
     if (validate(m)) return -1;
     s->m = m;
     if (o) s->o = *o; else or_default_options(&s->o);
+    if ((s->o.k_A_rho != 0 && s->o.k_A_rho != 1) ||
+        (s->o.k_A_rho && (s->o.k_A != 1.0 || !(s->o.k_A_lowest > 0.0) || !(s->o.k_A_highest > 0.0) ||
+                          !isfinite(s->o.k_A_lowest) || !isfinite(s->o.k_A_highest))))
+        return -1;
     if (!(s->o.k_A > 0.0) || !(s->o.k_S > 0.0) || !isfinite(s->o.k_A) || !isfinite(s->o.k_S) ||
         !(fabs(s->o.g_E) < 1.0) || !(fabs(s->o.g_S) < 1.0) || s->o.ffi < 0 || s->o.ffi > 2)
         return -1;
@@ -283,7 +289,8 @@ static int state_init(ostate *s, const or_model *m, const or_options *o) {
     s->lnG = calloc(nt, sizeof(double));
     s->D = calloc((size_t)nt * K, sizeof(double));
     s->q = calloc(K, sizeof(double));
-    if (!s->R || !s->rho || !s->M || !s->w || !s->kA || !s->kS || !s->g || !s->alb ||
+    s->kAsh = calloc(s->nsh, sizeof(double));
+    if (!s->kAsh || !s->R || !s->rho || !s->M || !s->w || !s->kA || !s->kS || !s->g || !s->alb ||
         !s->cdf[0] || !s->cdf[1] || !s->Tg || !s->lnT || !s->G || !s->lnG || !s->D || !s->q) {
         state_free(s);
         return -3;
@@ -295,6 +302,26 @@ static int state_init(ostate *s, const or_model *m, const or_options *o) {
         double r0 = m->r_edges[i], r1 = m->r_edges[i + 1];
         s->rho[i + s->cav] = m->rho[i];
         s->M[i + s->cav] = m->rho[i] * 4.0 / 3.0 * OR_PI * (r1 * r1 * r1 - r0 * r0 * r0);
+    }
+    /* absorption free-path scaling per shell (Eq. 8): constant k_A, or k_A(rho)
+     * linear in log rho from k_A_lowest at the lowest density of the model to
+     * k_A_highest at the highest (k_A_highest everywhere when all densities
+     * are equal; the empty cavity carries no absorption) */
+    {
+        double lo = INFINITY, hi = -INFINITY;
+        for (int i = 0; i < s->nsh; ++i)
+            if (s->rho[i] > 0.0) { lo = fmin(lo, log(s->rho[i])); hi = fmax(hi, log(s->rho[i])); }
+        s->kscale = s->o.k_S != 1.0;
+        for (int i = 0; i < s->nsh; ++i) {
+            double k = s->o.k_A;
+            if (s->o.k_A_rho) {
+                k = s->o.k_A_highest;
+                if (s->rho[i] > 0.0 && hi > lo)
+                    k = s->o.k_A_lowest + (s->o.k_A_highest - s->o.k_A_lowest) * (log(s->rho[i]) - lo) / (hi - lo);
+            }
+            s->kAsh[i] = k;
+            if (k != 1.0) s->kscale = 1;
+        }
     }
     /* dust: kappa_S = kappa_A a / (1 - a) so that a = kappa_S / (kappa_A + kappa_S) */
     trapezoid_weights(K, m->nu, s->w);
@@ -350,6 +377,9 @@ void or_default_options(or_options *o) {
     o->g_S = 0.0;
     o->k_A = 1.0;
     o->k_S = 1.0;
+    o->k_A_rho = 0;
+    o->k_A_lowest = 3.0;
+    o->k_A_highest = 1.0;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -611,14 +641,16 @@ static void trace_package(const ostate *s, tally_t *t, int src, uint64_t pid, ui
         d[0] = sqrt(fmax(0.0, 1.0 - mu * mu)); d[1] = 0.0; d[2] = mu;
         i = 0;
     }
-    /* free paths drawn from k e^{-k tau} (Eq. 8) carry the weight of the
-     * realised outcome when the flight ends: with two competing clocks, the
-     * factor (1/k) e^{(k-1) tau} of the clock that fired times the survival
-     * ratio e^{(k'-1) tau'} of the one that did not (both survive at escape) */
-    const double kA = s->o.k_A, kS = s->o.k_S;
-    const int kscale = kA != 1.0 || kS != 1.0;
+    /* Free paths drawn from k e^{-k tau} (Eq. 8), with k the same everywhere
+     * or, for absorption, a function of the local density: the absorption
+     * clock runs down a standard exponential depth at k_i times the true rate
+     * in shell i, the scattering clock at k_S times it.  The realised outcome
+     * carries, when the flight ends, the weight true / modified probability:
+     * the fired clock's 1/k times e^{modified - true depth} of both clocks. */
+    const double kS = s->o.k_S;
     int kw;                      /* this flight's free paths are k-scaled */
-    double tA0, tS0;             /* the depths drawn for this flight */
+    double tA0, tS0;             /* the depths drawn for this flight (absorption: modified depth) */
+    double trA = 0.0;            /* true absorption depth traversed in this flight */
     if (s->o.ffi) {
         double tau0 = ray_depth(s, x, d, i, k);
         if (!(tau0 > 0.0)) {
@@ -638,9 +670,9 @@ static void trace_package(const ostate *s, tally_t *t, int src, uint64_t pid, ui
         else { tauA = tau * (1.0 - s->alb[k]); tauS = INFINITY; }
         kw = 0;
     } else {
-        tauA = -log(u[2]) / kA;
+        tauA = -log(u[2]);
         tauS = -log(u[3]) / kS;
-        kw = kscale;
+        kw = s->kscale;
     }
     tA0 = tauA;
     tS0 = tauS;
@@ -651,15 +683,18 @@ static void trace_package(const ostate *s, tally_t *t, int src, uint64_t pid, ui
         int dir;
         double lb = boundary_distance(s, x, d, i, &dir);
         double chiA = s->kA[k] * s->rho[i], chiS = s->kS[k] * s->rho[i];
-        double lA = chiA > 0.0 ? tauA / chiA : INFINITY;
+        const double kAi = kw ? s->kAsh[i] : 1.0;
+        const double chiAm = kAi * chiA;          /* rate of the (modified) absorption clock */
+        double lA = chiAm > 0.0 ? tauA / chiAm : INFINITY;
         double lS = chiS > 0.0 ? tauS / chiS : INFINITY;
         if (lb < fmin(lA, lS)) {
             for (int j = 0; j < 3; ++j) x[j] += lb * d[j];
-            tauA -= chiA * lb;
+            tauA -= chiAm * lb;
             tauS -= chiS * lb;
+            trA += chiA * lb;
             i += dir;
             if (i >= s->nsh) {
-                if (kw) W *= exp((kA - 1.0) * (tA0 - tauA) + (kS - 1.0) * (tS0 - tauS));
+                if (kw) W *= exp((tA0 - tauA) - trA + (kS - 1.0) * (tS0 - tauS));
                 tally_escape(t, K, src, k, eps * W, events == 0);
                 t->st.n_escape++;
                 if (events == 0) t->st.n_direct++;
@@ -669,8 +704,13 @@ static void trace_package(const ostate *s, tally_t *t, int src, uint64_t pid, ui
             continue;
         }
         if (kw) {
-            if (lA <= lS) W *= exp((kA - 1.0) * tA0 + (kS - 1.0) * (tS0 - (tauS - chiS * lA))) / kA;
-            else W *= exp((kS - 1.0) * tS0 + (kA - 1.0) * (tA0 - (tauA - chiA * lS))) / kS;
+            if (lA <= lS) {
+                trA += chiA * lA;
+                W *= exp(tA0 - trA + (kS - 1.0) * (tS0 - (tauS - chiS * lA))) / kAi;
+            } else {
+                trA += chiA * lS;
+                W *= exp((tA0 - (tauA - chiAm * lS)) - trA + (kS - 1.0) * tS0) / kS;
+            }
         }
         if (events >= s->o.max_events) {
             t->st.terminated += eps * W;
@@ -739,11 +779,12 @@ static void trace_package(const ostate *s, tally_t *t, int src, uint64_t pid, ui
             perp_unit(xh, e);
             double sn = sqrt(fmax(0.0, 1.0 - mu * mu));
             for (int j = 0; j < 3; ++j) d[j] = mu * xh[j] + sn * e[j];
-            tauA = -log(u[3]) / kA;
+            tauA = -log(u[3]);
             tauS = -log(u2[0]) / kS;
-            kw = kscale;
+            kw = s->kscale;
             tA0 = tauA;
             tS0 = tauS;
+            trA = 0.0;
         } else {
             /* scattering (Sect. 2.1, Henyey-Greenstein phase function) */
             for (int j = 0; j < 3; ++j) x[j] += lS * d[j];
@@ -758,11 +799,12 @@ static void trace_package(const ostate *s, tally_t *t, int src, uint64_t pid, ui
                 double ph = 2.0 * OR_PI * u[1];
                 scatter_direction(x, d, ct, ph);
             }
-            tauA = -log(u[2]) / kA;
+            tauA = -log(u[2]);
             tauS = -log(u[3]) / kS;
-            kw = kscale;
+            kw = s->kscale;
             tA0 = tauA;
             tS0 = tauS;
+            trA = 0.0;
         }
         if (W < s->o.w_floor * W0) {
             t->st.terminated += eps * W;

@@ -60,6 +60,9 @@ typedef struct or_options {
     int32_t use_g_S;        /* scattering directions from HG(g_S) about the reference direction (Eq. 7) */
     double g_S;
     double k_A, k_S;        /* free paths from k e^{-k tau} (Eq. 8); 1 = unweighted */
+    int32_t k_A_rho;        /* absorption scaling linear in log rho (Sect. 3.2): k_A_lowest at the
+                               lowest density of the model, k_A_highest at the highest (k_A must be 1) */
+    double k_A_lowest, k_A_highest;
 } or_options;
 
 typedef struct or_stats {

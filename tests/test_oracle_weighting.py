@@ -145,3 +145,49 @@ def test_weighted_energy_balance(orc, opts):
         out.append((sum(st["escaped"]) + st["ffi_escaped"] + st["terminated"]) / st["L_ps"])
     out = np.array(out)
     assert abs(out.mean() - 1) <= 5 * out.std(ddof=1) / math.sqrt(R) + 1e-4, out
+
+
+def _graded_gray(albedo):
+    """Gray sphere, central source, density falling 30x outwards (k_A(rho) varies)."""
+    m = wl.gray_model(10, 1.5, external=False, r_in=0.05 * wl.R_OUT)
+    m["rho"] = m["rho"] * np.geomspace(3.0, 0.1, 10)
+    m["albedo"] = np.full(len(m["nu"]), albedo)
+    return m
+
+
+@pytest.mark.parametrize("opts", [dict(k_A_rho=1), dict(k_A_rho=1, k_A_lowest=0.6, k_A_highest=2.0),
+                                  dict(k_A_rho=1, k_S=1.5)])
+def test_density_dependent_kA_first_absorption(orc, opts):
+    m = _graded_gray(0.4)
+    p = _first_event_probabilities(m, 0.4)
+    N, R = 40_000, 8
+    fa = np.stack([orc.run(m, n_ps=N, seed=s, first_abs=True, **opts)["first_abs"] / m["L_ps"]
+                   for s in range(1, R + 1)])
+    mean, sem = fa.mean(axis=0), fa.std(axis=0, ddof=1) / math.sqrt(R)
+    assert np.all(np.abs(mean - p) <= 5 * sem + 1e-3 * p), (mean, p, sem)
+
+
+def test_density_dependent_kA_energy_balance(orc):
+    m = _graded_gray(0.4)
+    out = []
+    for s in range(1, 9):
+        st = orc.run(m, n_ps=30_000, seed=s, k_A_rho=1)["stats"]
+        out.append((sum(st["escaped"]) + st["ffi_escaped"] + st["terminated"]) / st["L_ps"])
+    out = np.array(out)
+    assert abs(out.mean() - 1) <= 5 * out.std(ddof=1) / math.sqrt(8) + 1e-4, out
+
+
+def test_density_dependent_kA_against_brute_force(orc):
+    from oracle import bruteforce as bf
+    m = wl.central_source(n=3, tau_V=30.0, p=1.0, r_in=10 * wl.AU)
+    m["albedo"] = np.zeros(64)
+    ref = bf.solve_central(m)
+    e = orc.ensemble(m, n_ps=300_000, seeds=range(1, 9), reemit_uniform=1, k_A_rho=1)
+    mean = e["T"].mean(axis=0)
+    sem = e["T"].std(axis=0, ddof=1) / math.sqrt(8)
+    assert np.all(np.abs(mean - ref["T"]) <= 4.5 * sem + 2e-4 * ref["T"]), (mean, ref["T"], sem)
+
+
+def test_density_dependent_kA_rejects_constant_kA(orc):
+    with pytest.raises(ValueError):
+        orc.run(wl.cfg_external_small(), n_ext=10, k_A_rho=1, k_A=2.0)
