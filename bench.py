@@ -71,7 +71,7 @@ def cpu_baseline(model: dict, key: str, n_pkg_per_seed: int, seeds: int, steppin
     oracle.ensemble(model, seeds=range(1, seeds + 1), threads=threads, **kw)
     dt = time.perf_counter() - t0
     return {"value": seeds * n_pkg_per_seed / dt, "unit": "packages/s", "cores": threads, "kind": "oracle",
-            "sample": f"{seeds} independent seeds x {n_pkg_per_seed:.0e} packages of the same cloud, "
+            "sample": f"{seeds} independent seeds x {n_pkg_per_seed:,} packages of the same cloud, "
                       f"serial FP64 oracle, {threads} threads, {dt:.1f} s wall ({stepping_note})"}
 
 

@@ -67,6 +67,10 @@ typedef struct ire_options {
     double g_S;
     double k_A, k_S;      /* Eq. 8: free paths from k e^{-k tau} (> 0; 1 = unweighted); the weight of a flight
                              is the fired clock's (1/k) e^{(k-1) tau} times the other's e^{(k'-1) tau'} */
+    int32_t k_A_rho;      /* Sect. 3.2: absorption scaling linear in log rho, k_A_lowest at the model's lowest
+                             density, k_A_highest at its highest (k_A must be 1); the weight is the fired
+                             clock's 1/k times e^{modified - true absorption depth} */
+    double k_A_lowest, k_A_highest;
 } ire_options;
 
 typedef struct ire_stats {
@@ -82,7 +86,7 @@ typedef struct ire_stats {
 
 /* Fill *o with the defaults: k_bg 0.5, ffi 0, w_floor 1e-10, max_events 1e6,
  * stepping IRE_FP32, max_lanes 0, reemit_uniform 0, aggregate 1, batch 0,
- * use_g_E 0, g_E 0, use_g_S 0, g_S 0, k_A 1, k_S 1. */
+ * use_g_E 0, g_E 0, use_g_S 0, g_S 0, k_A 1, k_S 1, k_A_rho 0, k_A_lowest 3, k_A_highest 1. */
 int ire_default_options(ire_options *o);
 
 /* Create a handle bound to HIP device `hip_device`; *out is owned by the caller
@@ -192,7 +196,7 @@ typedef struct ire_batch_options {
     int32_t reemit_uniform;
     int32_t aggregate;
     int32_t batch;            /* lanes parked at an event before the wave processes events (0 = 32) */
-    uint64_t item_packages;   /* packages per work item; a model is split into items (0 = 65536) */
+    uint64_t item_packages;   /* packages per work item; a model is split into items (0 = 524288) */
     int32_t use_graph;        /* 1: replay zero/trace/finalize as a captured HIP graph (default) */
     int32_t use_g_E;          /* weighted sampling, as ire_options */
     double g_E;
@@ -209,7 +213,7 @@ typedef struct ire_batch_stats {
     float ms_run;              /* zero + trace + finalize on the device (HIP events) */
 } ire_batch_stats;
 
-/* Defaults: as ire_default_options, item_packages 65536, use_graph 1. */
+/* Defaults: as ire_default_options, item_packages 524288, use_graph 1. */
 int ire_batch_default_options(ire_batch_options *o);
 int ire_batch_create(int hip_device, ire_batch **out);
 void ire_batch_destroy(ire_batch *b);
@@ -229,9 +233,10 @@ int ire_batch_set_options(ire_batch *b, const ire_batch_options *o);
 int ire_batch_run(ire_batch *b, void *hip_stream);
 /* Synchronise and copy A_flat[sum n_shells] (erg/s) and T_flat (K); either may be NULL. */
 int ire_batch_get(ire_batch *b, double *A_flat, double *T_flat, ire_batch_stats *stats);
-/* Time candidate schedules (parking threshold x item size) on a sample of the
- * models with package budgets scaled by `fraction` (0 < fraction <= 1), keep
- * the fastest in the batch options and in *chosen (may be NULL).  With a
+/* Time candidate schedules (parking threshold 24/32/48 x item size 65536 ..
+ * 1048576) on every model with package budgets and item sizes scaled by
+ * `fraction` (0 < fraction <= 1), keep the fastest in the batch options and
+ * in *chosen (may be NULL).  With a
  * cache_path, a previous choice for the same device and model class is reused
  * and new choices are stored (JSON). */
 int ire_batch_autotune(ire_batch *b, double fraction, const char *cache_path, ire_batch_options *chosen);

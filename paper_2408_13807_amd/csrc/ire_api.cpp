@@ -42,6 +42,8 @@ struct ire_model {
     // device buffers
     DevBuf<ire::ShellF> shf;
     DevBuf<ire::ShellD> shd;
+    DevBuf<float2> rkf;
+    DevBuf<double2> rkd;
     DevBuf<ire::DustF> dustf;
     DevBuf<ire::DustD> dustd;
     DevBuf<float> cdff, Gf, Df;
@@ -93,6 +95,10 @@ int build_tables(ire_model *m) {
     std::vector<ire::ShellD> shd;
     std::vector<double> invM;
     ire::host::build_shell_table(m->r_edges.data(), m->rho.data(), n, shf, shd, invM);
+    std::vector<float2> rkf;
+    std::vector<double2> rkd;
+    ire::host::build_absorption_scaling(m->r_edges.data(), m->rho.data(), n, m->opt.k_A_lowest, m->opt.k_A_highest,
+                                        rkf, rkd);
     const std::vector<ire::DustF> &df = dt.df;
     const std::vector<ire::DustD> &dd = dt.dd;
     const std::vector<double> &G = dt.G, &D = dt.D, &w = dt.w;
@@ -123,7 +129,8 @@ int build_tables(ire_model *m) {
         (e = m->Gf.upload(Gf)) != hipSuccess || (e = m->Gd.upload(G)) != hipSuccess ||
         (e = m->Df.upload(Df)) != hipSuccess || (e = m->Dd.upload(D)) != hipSuccess ||
         (e = m->invM.upload(invM)) != hipSuccess || (e = m->lnGd.upload(m->lnG)) != hipSuccess ||
-        (e = m->lnTd.upload(m->lnT)) != hipSuccess || (e = m->guide.upload(guide)) != hipSuccess)
+        (e = m->lnTd.upload(m->lnT)) != hipSuccess || (e = m->guide.upload(guide)) != hipSuccess ||
+        (e = m->rkf.upload(rkf)) != hipSuccess || (e = m->rkd.upload(rkd)) != hipSuccess)
         return e == hipErrorOutOfMemory ? m->fail(IRE_E_NOMEM, "device allocation failed")
                                         : m->hip_fail(e, "table upload");
     if ((e = m->A.ensure((size_t)n * ire::kAccStride)) != hipSuccess ||
@@ -165,6 +172,9 @@ int ire_default_options(ire_options *o) {
     o->g_S = 0.0;
     o->k_A = 1.0;
     o->k_S = 1.0;
+    o->k_A_rho = 0;
+    o->k_A_lowest = 3.0;
+    o->k_A_highest = 1.0;
     return IRE_OK;
 }
 
@@ -203,7 +213,7 @@ void ire_destroy(ire_model *m) {
     (void)hipDeviceSynchronize();
     m->shf.release(); m->shd.release(); m->dustf.release(); m->dustd.release();
     m->cdff.release(); m->Gf.release(); m->Df.release(); m->cdfd.release(); m->Gd.release();
-    m->Dd.release(); m->invM.release(); m->lnGd.release(); m->lnTd.release(); m->guide.release(); m->sed.release(); m->A.release();
+    m->Dd.release(); m->invM.release(); m->lnGd.release(); m->lnTd.release(); m->guide.release(); m->sed.release(); m->rkf.release(); m->rkd.release(); m->A.release();
     m->A_out.release(); m->T_out.release(); m->stats.release();
     if (m->ev0) (void)hipEventDestroy(m->ev0);
     if (m->ev1) (void)hipEventDestroy(m->ev1);
@@ -310,6 +320,11 @@ int ire_set_options(ire_model *m, const ire_options *o) {
     if (o->ffi < 0 || o->ffi > 2) return m->fail(IRE_E_INVALID, "ffi must be 0, 1 or 2");
     const std::string we = ire::host::check_weights(o->use_g_E, o->g_E, o->use_g_S, o->g_S, o->k_A, o->k_S);
     if (!we.empty()) return m->fail(IRE_E_INVALID, "%s", we.c_str());
+    if (o->k_A_rho != 0 && o->k_A_rho != 1) return m->fail(IRE_E_INVALID, "k_A_rho must be 0 or 1");
+    if (o->k_A_rho && (o->k_A != 1.0 || !(o->k_A_lowest > 0.0) || !(o->k_A_highest > 0.0) ||
+                       !std::isfinite(o->k_A_lowest) || !std::isfinite(o->k_A_highest)))
+        return m->fail(IRE_E_INVALID, "k_A_rho needs k_A = 1 and finite k_A_lowest, k_A_highest > 0");
+    if (o->k_A_lowest != m->opt.k_A_lowest || o->k_A_highest != m->opt.k_A_highest) m->dirty = true;
     if (o->reemit_uniform != 0 && o->reemit_uniform != 1) return m->fail(IRE_E_INVALID, "reemit_uniform must be 0 or 1");
     if (o->aggregate != 0 && o->aggregate != 1) return m->fail(IRE_E_INVALID, "aggregate must be 0 or 1");
     if (o->batch < 0 || o->batch > 64) return m->fail(IRE_E_INVALID, "batch must be in [0, 64]");
@@ -398,6 +413,7 @@ int ire_advance(ire_model *m, uint64_t n_ext, uint64_t n_ps, void *hip_stream) {
     p.w_floor = m->opt.w_floor; p.max_events = m->opt.max_events; p.max_lanes = m->opt.max_lanes;
     p.use_g_E = m->opt.use_g_E; p.g_E = m->opt.g_E; p.use_g_S = m->opt.use_g_S; p.g_S = m->opt.g_S;
     p.k_A = m->opt.k_A; p.k_S = m->opt.k_S;
+    p.k_A_rho = m->opt.k_A_rho; p.rkf = m->rkf.p; p.rkd = m->rkd.p;
     p.A = m->A.p; p.stats = m->stats.p; p.sed = m->sed.p;
     {
         const unsigned long long waves = (unsigned long long)grid * (block / 64);

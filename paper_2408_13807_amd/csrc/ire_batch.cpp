@@ -154,7 +154,7 @@ int prepare(ire_batch *b) {
     b->n_shells = d_off;
 
     // work items, most expensive first
-    const unsigned long long item = b->opt.item_packages ? b->opt.item_packages : 65536ull;
+    const unsigned long long item = b->opt.item_packages ? b->opt.item_packages : 524288ull;
     b->items.clear();
     std::vector<double> icost;
     for (size_t m = 0; m < b->models.size(); ++m) {
@@ -339,7 +339,7 @@ int ire_batch_default_options(ire_batch_options *o) {
     o->reemit_uniform = 0;
     o->aggregate = 1;
     o->batch = 0;
-    o->item_packages = 65536;
+    o->item_packages = 524288;
     o->use_graph = 1;
     o->use_g_E = 0;
     o->g_E = 0.0;
@@ -550,15 +550,17 @@ int ire_batch_autotune(ire_batch *b, double fraction, const char *cache_path, ir
     const ire_batch_options saved = b->opt;
     b->models = sample;
     b->dirty = true;
-    const int batches[] = {16, 24, 32, 48};
-    const unsigned long long items[] = {16384ull, 65536ull, 262144ull};
+    // candidate work-item sizes are scaled with the budgets, so that the
+    // sample splits every model into as many items as the full run would
+    const int batches[] = {24, 32, 48};
+    const unsigned long long items[] = {65536ull, 262144ull, 524288ull, 1048576ull};
     float best_ms = 1e30f;
     int rc = IRE_OK;
     for (int bt : batches) {
         for (unsigned long long it : items) {
             ire_batch_options o = saved;
             o.batch = bt;
-            o.item_packages = it;
+            o.item_packages = std::max<unsigned long long>(64ull, (unsigned long long)std::llround((double)it * fraction));
             o.use_graph = 0;
             if ((rc = ire_batch_set_options(b, &o))) break;
             if ((rc = run_on(b, nullptr))) break;
@@ -569,6 +571,7 @@ int ire_batch_autotune(ire_batch *b, double fraction, const char *cache_path, ir
             if (st.ms_run < best_ms) {
                 best_ms = st.ms_run;
                 best = o;
+                best.item_packages = it;
             }
         }
         if (rc) break;

@@ -167,6 +167,33 @@ inline void build_shell_table(const double *r_edges, const double *rho, int n, s
     }
 }
 
+// Density-dependent absorption scaling (Sect. 3.2): per record of a shell
+// table built by build_shell_table, {k rho, 1/(k rho)} in the same units, with
+// k linear in log rho from k_lowest at the lowest density of the model to
+// k_highest at the highest (k_highest when all densities are equal); the
+// cavity has zero density, the sentinels infinite density.
+inline void build_absorption_scaling(const double *r_edges, const double *rho, int n, double k_lowest,
+                                     double k_highest, std::vector<float2> &rkf, std::vector<double2> &rkd) {
+    const double Rout = r_edges[n];
+    const int cav = r_edges[0] > 0.0 ? 1 : 0;
+    double lo = HUGE_VAL, hi = -HUGE_VAL;
+    for (int i = 0; i < n; ++i)
+        if (rho[i] > 0.0) { lo = std::min(lo, std::log(rho[i])); hi = std::max(hi, std::log(rho[i])); }
+    rkf.assign((size_t)n + cav + kSentinels, float2{0.0f, 0.0f});
+    rkd.assign((size_t)n + cav + kSentinels, double2{0.0, 0.0});
+    for (int i = 0; i < n; ++i) {
+        double k = k_highest;
+        if (rho[i] > 0.0 && hi > lo) k = k_lowest + (k_highest - k_lowest) * (std::log(rho[i]) - lo) / (hi - lo);
+        const double ra = k * rho[i] * Rout;
+        rkd[cav + i] = double2{ra, ra > 0.0 ? 1.0 / ra : 0.0};
+        rkf[cav + i] = float2{(float)ra, ra > 0.0 ? (float)(1.0 / ra) : 0.0f};
+    }
+    for (int j = 0; j < kSentinels; ++j) {
+        rkd[cav + n + j] = double2{HUGE_VAL, 0.0};
+        rkf[cav + n + j] = float2{HUGE_VALF, 0.0f};
+    }
+}
+
 // Device buffer that grows on demand.
 template <typename T>
 struct DevBuf {

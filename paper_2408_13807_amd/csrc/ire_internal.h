@@ -77,6 +77,9 @@ struct TraceParams {
     unsigned long long max_events;
     int use_g_E, use_g_S;             // weighted sampling (Table 1)
     double g_E, g_S, k_A, k_S;
+    int k_A_rho;                      // absorption scaling by density: per-shell {k rho, 1/(k rho)} below
+    const float2 *rkf;                // cavity + n + kSentinels records (table units), FP32 path
+    const double2 *rkd;               // the same, FP64 path
     int max_lanes;                    // 0 = no limit
     unsigned long long chunk;         // package indices a wave takes from the cursor at once (>= 64)
     int batch;                        // parked lanes that trigger an event pass (1..64)

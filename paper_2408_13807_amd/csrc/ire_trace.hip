@@ -76,6 +76,7 @@ template <typename R> struct P;
 template <> struct P<float> {
     using Shell = ShellF;
     using Dust = DustF;
+    using KRec = float2;   // per shell: {k rho, 1 / (k rho)} of the scaled absorption clock
     // one 128-bit load of a shell record
     static __device__ __forceinline__ ShellF shell(const ShellF *q) {
         const float4 v = *reinterpret_cast<const float4 *>(q);
@@ -100,6 +101,7 @@ template <> struct P<float> {
 template <> struct P<double> {
     using Shell = ShellD;
     using Dust = DustD;
+    using KRec = double2;
     static __device__ __forceinline__ ShellD shell(const ShellD *q) { return *q; }
     static __device__ __forceinline__ double uni(uint32_t x) { return ((double)x + 0.5) * 0x1p-32; }
     static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
@@ -285,15 +287,23 @@ struct MethodOpts {
 // Trace every package of one model with the lanes of this wave.  Package
 // indices come from `cursor` (global or LDS memory) `chunk` at a time; the
 // call returns when the cursor is exhausted and every lane is idle.
-template <typename R, bool AGG, bool WTD>
+template <typename R, bool AGG, int WT>
 __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodOpts &o,
                                             const typename P<R>::Dust *dust, const R *cdf,
                                             const R *G, const R *D, int K, int n_t,
                                             const unsigned char *guide, float g_lg0, float g_scale,
+                                            const typename P<R>::KRec *rk,
                                             unsigned long long *cursor, unsigned long long chunk,
                                             bool lane_off, LaneCounters &lc, double *sed) {
     using Shell = typename P<R>::Shell;
     using Dust = typename P<R>::Dust;
+    using KRec = typename P<R>::KRec;
+    // WT: 0 plain; 1 weighted sampling (Table 1) with constant free-path
+    // scaling; 2 also an absorption scaling that depends on the shell's
+    // density, so the two free paths fall at different rates in every shell
+    // and each flight carries two columns
+    constexpr bool WTD = WT >= 1;
+    constexpr bool KRHO = WT == 2;
     // lane status: in flight, parked at an interaction (or at the surface),
     // without a package, finished (no packages left)
     enum : int { ST_FLY = 0, ST_EVT = 1, ST_DEAD = 3, ST_DONE = 4 };
@@ -318,6 +328,8 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
     int st = lane_off ? ST_DONE : ST_DEAD;
     const Shell *ps = sh;          // current shell
     Shell cur = P<R>::shell(sh);   // its record, kept in registers while the package flies
+    KRec curk{};                   // its scaled absorption rate (k_A(rho) only)
+    if constexpr (KRHO) curk = rk[0];
     int k = 0, src = 0;
     R b2 = 0, t = 0, W = 1, W0 = 1;
     R sig = 0;                     // column (rho-weighted length) left before the next interaction
@@ -327,11 +339,15 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
     unsigned long long events = 0;
     // scaled free paths (Eq. 8): the flight's drawn column and whether its
     // free paths were scaled (not for the forced first flight)
-    const bool kscale = WTD && (o.k_A != 1.0 || o.k_S != 1.0);
+    const bool kscale = KRHO || (WTD && (o.k_A != 1.0 || o.k_S != 1.0));
     const R kA1 = (R)(o.k_A - 1.0), kS1 = (R)(o.k_S - 1.0);
     const R inv_kA = (R)(1.0 / o.k_A), inv_kS = (R)(1.0 / o.k_S);
     R sig0 = 0;
     bool kw = false;
+    // k_A(rho): the absorption clock's column left (units of k rho l) and drawn;
+    // sig, sig0 then hold the scattering clock's (units of rho l, infinite where
+    // the dust does not scatter); colT is the rho l column the flight has crossed
+    R sigA = 0, sigA0 = 0, colT = 0;
 
     // One boundary step of a package in flight (Eq. 4), computed for every
     // lane and committed only where the package is in flight.  Both free
@@ -349,13 +365,24 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
         const bool inward = (t < (R)0) && (b2 < cur.r2_in);
         const Shell *const pn = inward ? ps - 1 : ps + 1;
         const Shell nx = P<R>::shell(pn);
+        KRec nxk{};
+        if constexpr (KRHO) nxk = rk[pn - sh];
         const R arg = (inward ? cur.r2_in : cur.r2_out) - b2;
         const R sq = P<R>::sqrt_(arg > (R)0 ? arg : (R)0);
         const R tn = inward ? -sq : sq;
         const R ds = cur.rho * (tn - t);
-        const bool cross = ds < sig;
+        bool cross = ds < sig;
+        R dsA = 0;
+        if constexpr (KRHO) {
+            dsA = curk.x * (tn - t);
+            cross = cross && dsA < sigA;
+        }
         const bool mv = f && cross;
         sig = mv ? sig - ds : sig;
+        if constexpr (KRHO) {
+            sigA = mv ? sigA - dsA : sigA;
+            colT = mv ? colT + ds : colT;
+        }
         t = mv ? tn : t;
         ps = mv ? pn : ps;
         lc.cross += mv ? 1u : 0u;
@@ -367,6 +394,10 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
         cur.r2_out = mv ? nx.r2_out : cur.r2_out;
         cur.rho = mv ? nx.rho : cur.rho;
         cur.inv_rho = mv ? nx.inv_rho : cur.inv_rho;
+        if constexpr (KRHO) {
+            curk.x = mv ? nxk.x : curk.x;
+            curk.y = mv ? nxk.y : curk.y;
+        }
     };
 
     // The event pass: escapes, the event-count limit, refills from the wave's
@@ -378,11 +409,34 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
             bool absorbing = false, scattering = false;
             // a parked package still stands where its last step began: move it
             // along the column left to the interaction point
-            if (st == ST_EVT) t += sig * cur.inv_rho;
+            if constexpr (KRHO) {
+                // two columns: the clock that runs out first in this shell fires
+                if (st == ST_EVT) {
+                    if (kw) {
+                        const bool esc = ps == sentinel;
+                        const R lS = sig * cur.inv_rho, lA = sigA * curk.y;
+                        const R lev = lA < lS ? lA : lS;
+                        ev_abs = lA <= lS;
+                        t += lev;
+                        // weight: e^{modified - true absorption depth} e^{(k_S - 1) tau_S} and the
+                        // fired clock's 1/k (1/k_i = rho / (k rho) of this shell)
+                        const Dust dk = dust[k];
+                        const R cS = esc ? colT : colT + cur.rho * lev;
+                        const R cA = esc ? sigA0 - sigA : sigA0 - sigA + curk.x * lev;
+                        R f = P<R>::exp_(dk.kA * (cA - cS) + kS1 * dk.kS * cS);
+                        if (!esc) f *= ev_abs ? cur.rho * curk.y : inv_kS;
+                        W *= f;
+                    } else {
+                        t += sig * cur.inv_rho;   // a forced first flight: one column, type drawn
+                    }
+                }
+            } else {
+                if (st == ST_EVT) t += sig * cur.inv_rho;
+            }
             // scaled free paths: the weight of the flight's outcome, the fired
             // clock's (1/k) e^{(k-1) tau} times the survival ratio e^{(k'-1) tau'}
             // of the other (both survival ratios at escape); tau = kappa x column
-            if (WTD && kscale && st == ST_EVT && kw) {
+            if (WTD && !KRHO && kscale && st == ST_EVT && kw) {
                 const Dust dk = dust[k];
                 const bool esc = ps == sentinel;
                 const R c = esc ? sig0 - sig : sig0;
@@ -629,6 +683,13 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
                 const R sS = tauS * d.inv_kS;
                 ev_abs = sA <= sS;
                 sig = ev_abs ? sA : sS;
+                if constexpr (KRHO) {
+                    // scaled flights carry both columns; the forced first flight one
+                    sigA = kw_new ? sA : P<R>::inf();
+                    sig = kw_new ? sS : sig;
+                    sigA0 = sigA;
+                    colT = 0;
+                }
                 sig0 = sig;
                 kw = kw_new;
                 st = ST_FLY;
@@ -639,7 +700,7 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
         // ---- crossing sweep: packages in flight step from boundary to boundary;
         // a package that reaches its interaction parks, and the wave stops stepping
         // when enough of its packages are parked to process their events together.
-        // Two steps per check: a step of a parked package changes nothing.
+        // Four steps per check: a step of a parked package changes nothing.
         {
             const int live = __popcll(__ballot(st != ST_DONE));
             const int half = (live + 1) / 2;
@@ -647,6 +708,8 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
             for (;;) {
                 const int nfly = __popcll(__ballot(st == ST_FLY));
                 if (nfly == 0 || live - nfly >= want) break;
+                step();
+                step();
                 step();
                 step();
             }
@@ -657,6 +720,7 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
         // ---- event batch
         event_pass();
         cur = P<R>::shell(ps);
+        if constexpr (KRHO) curk = rk[ps - sh];
     }
 }
 
@@ -715,7 +779,7 @@ __device__ __forceinline__ void single_model(const TraceParams &p, const typenam
     o.k_S = p.k_S;
 }
 
-template <bool AGG, bool WTD>
+template <bool AGG, int WT>
 __global__ __launch_bounds__(kBlockFP32) void ire_trace_f32(TraceParams p) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int nsh = p.n + p.cavity + kSentinels, K = p.K, n_t = p.n_t;
@@ -735,20 +799,23 @@ __global__ __launch_bounds__(kBlockFP32) void ire_trace_f32(TraceParams p) {
     for (int j = threadIdx.x; j < ng; j += blockDim.x) s_guide[j] = reinterpret_cast<const uint32_t *>(p.guide)[j];
     double *s_sed = reinterpret_cast<double *>(s_guide + ng);
     for (int j = threadIdx.x; j < 4 * K; j += blockDim.x) s_sed[j] = 0.0;
+    float2 *s_rk = reinterpret_cast<float2 *>(s_sed + 4 * K);
+    if constexpr (WT == 2)
+        for (int j = threadIdx.x; j < nsh; j += blockDim.x) s_rk[j] = p.rkf[j];
     __syncthreads();
     ModelCtx<float> mc;
     MethodOpts o;
     single_model<float>(p, s_sh, mc, o);
     const long long gtid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     LaneCounters lc;
-    trace_model<float, AGG, WTD>(mc, o, s_dust, s_cdf, s_G, s_D, K, n_t, reinterpret_cast<const unsigned char *>(s_guide),
-                                 p.g_lg0, p.g_scale, &p.stats->cursor, p.chunk,
+    trace_model<float, AGG, WT>(mc, o, s_dust, s_cdf, s_G, s_D, K, n_t, reinterpret_cast<const unsigned char *>(s_guide),
+                                p.g_lg0, p.g_scale, s_rk, &p.stats->cursor, p.chunk,
                                  p.max_lanes > 0 && gtid >= p.max_lanes, lc, s_sed);
     flush_counters(lc, p.stats);
     flush_sed(s_sed, 4 * K, p.sed);
 }
 
-template <bool AGG, bool WTD>
+template <bool AGG, int WT>
 __global__ __launch_bounds__(256) void ire_trace_f64(TraceParams p) {
     extern __shared__ __align__(16) unsigned char smem[];
     double *s_sed = reinterpret_cast<double *>(smem);
@@ -759,8 +826,8 @@ __global__ __launch_bounds__(256) void ire_trace_f64(TraceParams p) {
     single_model<double>(p, p.shd, mc, o);
     const long long gtid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     LaneCounters lc;
-    trace_model<double, AGG, WTD>(mc, o, p.dustd, p.cdfd, p.Gd, p.Dd, p.K, p.n_t, p.guide, p.g_lg0, p.g_scale,
-                                  &p.stats->cursor, p.chunk, p.max_lanes > 0 && gtid >= p.max_lanes, lc, s_sed);
+    trace_model<double, AGG, WT>(mc, o, p.dustd, p.cdfd, p.Gd, p.Dd, p.K, p.n_t, p.guide, p.g_lg0, p.g_scale,
+                                 p.rkd, &p.stats->cursor, p.chunk, p.max_lanes > 0 && gtid >= p.max_lanes, lc, s_sed);
     flush_counters(lc, p.stats);
     flush_sed(s_sed, 4 * p.K, p.sed);
 }
@@ -813,7 +880,7 @@ __global__ void ire_finalize(FinalizeParams p) {
 // next to the shared dust / G / re-emission tables, traces the range with all
 // its waves (package indices from an LDS cursor), and drains before the next.
 
-template <bool AGG, bool WTD>
+template <bool AGG, int WT>
 __global__ __launch_bounds__(kBlockFP32) void ire_trace_batch(BatchParams p) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ unsigned long long s_item;
@@ -874,8 +941,9 @@ __global__ __launch_bounds__(kBlockFP32) void ire_trace_batch(BatchParams p) {
         mc.pid0[0] = item.first;
         mc.pid0[1] = item.first;
         mc.seed = bm.seed;
-        trace_model<float, AGG, WTD>(mc, o, s_dust, s_cdf, s_G, s_D, K, n_t,
-                                     reinterpret_cast<const unsigned char *>(s_guide), p.g_lg0, p.g_scale, &s_cursor,
+        trace_model<float, AGG, WT>(mc, o, s_dust, s_cdf, s_G, s_D, K, n_t,
+                                    reinterpret_cast<const unsigned char *>(s_guide), p.g_lg0, p.g_scale, nullptr,
+                                    &s_cursor,
                                      64ull, false, lc, nullptr);
     }
     flush_counters(lc, p.stats);
@@ -918,53 +986,65 @@ __global__ void ire_finalize_batch(BatchFinalizeParams p) {
 
 size_t trace_lds_bytes(int n_table, int K, int n_t) {
     return (size_t)n_table * sizeof(ShellF) + (size_t)K * sizeof(DustF) + (size_t)2 * K * sizeof(float) +
-           (size_t)n_t * sizeof(float) + (size_t)n_t * K * sizeof(float) + guide_bytes(n_t) + sed_lds_bytes(K);
+           (size_t)n_t * sizeof(float) + (size_t)n_t * K * sizeof(float) + guide_bytes(n_t) + sed_lds_bytes(K) +
+           (size_t)n_table * sizeof(float2);
 }
 
 size_t sed_lds_bytes(int K) { return (size_t)4 * K * sizeof(double); }
 
-static const void *f32_kernel(int aggregate, bool wtd) {
-    if (wtd) return aggregate ? reinterpret_cast<const void *>(&ire_trace_f32<true, true>)
-                              : reinterpret_cast<const void *>(&ire_trace_f32<false, true>);
-    return aggregate ? reinterpret_cast<const void *>(&ire_trace_f32<true, false>)
-                     : reinterpret_cast<const void *>(&ire_trace_f32<false, false>);
+static const void *f32_kernel(int aggregate, int wt) {
+    if (wt == 2) return aggregate ? reinterpret_cast<const void *>(&ire_trace_f32<true, 2>)
+                                  : reinterpret_cast<const void *>(&ire_trace_f32<false, 2>);
+    if (wt == 1) return aggregate ? reinterpret_cast<const void *>(&ire_trace_f32<true, 1>)
+                                  : reinterpret_cast<const void *>(&ire_trace_f32<false, 1>);
+    return aggregate ? reinterpret_cast<const void *>(&ire_trace_f32<true, 0>)
+                     : reinterpret_cast<const void *>(&ire_trace_f32<false, 0>);
 }
 
-static const void *batch_kernel(int aggregate, bool wtd) {
-    if (wtd) return aggregate ? reinterpret_cast<const void *>(&ire_trace_batch<true, true>)
-                              : reinterpret_cast<const void *>(&ire_trace_batch<false, true>);
-    return aggregate ? reinterpret_cast<const void *>(&ire_trace_batch<true, false>)
-                     : reinterpret_cast<const void *>(&ire_trace_batch<false, false>);
+static const void *batch_kernel(int aggregate, int wt) {
+    if (wt >= 1) return aggregate ? reinterpret_cast<const void *>(&ire_trace_batch<true, 1>)
+                                  : reinterpret_cast<const void *>(&ire_trace_batch<false, 1>);
+    return aggregate ? reinterpret_cast<const void *>(&ire_trace_batch<true, 0>)
+                     : reinterpret_cast<const void *>(&ire_trace_batch<false, 0>);
 }
 
-static const void *f64_kernel(int aggregate, bool wtd) {
-    if (wtd) return aggregate ? reinterpret_cast<const void *>(&ire_trace_f64<true, true>)
-                              : reinterpret_cast<const void *>(&ire_trace_f64<false, true>);
-    return aggregate ? reinterpret_cast<const void *>(&ire_trace_f64<true, false>)
-                     : reinterpret_cast<const void *>(&ire_trace_f64<false, false>);
+static const void *f64_kernel(int aggregate, int wt) {
+    if (wt == 2) return aggregate ? reinterpret_cast<const void *>(&ire_trace_f64<true, 2>)
+                                  : reinterpret_cast<const void *>(&ire_trace_f64<false, 2>);
+    if (wt == 1) return aggregate ? reinterpret_cast<const void *>(&ire_trace_f64<true, 1>)
+                                  : reinterpret_cast<const void *>(&ire_trace_f64<false, 1>);
+    return aggregate ? reinterpret_cast<const void *>(&ire_trace_f64<true, 0>)
+                     : reinterpret_cast<const void *>(&ire_trace_f64<false, 0>);
 }
 
-// The weighted-sampling instantiation is used only when an option needs it,
-// so that the default path keeps its register budget.
-template <typename Params>
-static bool weighted(const Params &p) {
-    return p.use_g_E || p.use_g_S || p.k_A != 1.0 || p.k_S != 1.0 || p.ffi == 2;
+// The weighted-sampling instantiations are used only when an option needs
+// them, so that the default path keeps its register budget.
+static int weighting(const TraceParams &p) {
+    if (p.k_A_rho) return 2;
+    return (p.use_g_E || p.use_g_S || p.k_A != 1.0 || p.k_S != 1.0 || p.ffi == 2) ? 1 : 0;
+}
+
+static int weighting(const BatchParams &p) {
+    return (p.use_g_E || p.use_g_S || p.k_A != 1.0 || p.k_S != 1.0 || p.ffi == 2) ? 1 : 0;
 }
 
 hipError_t trace_configure(int fp64, int aggregate, size_t lds) {
     if (fp64) return hipSuccess;
-    hipError_t e = hipFuncSetAttribute(f32_kernel(aggregate, false), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(f32_kernel(aggregate, true), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    for (int wt = 0; wt < 3; ++wt) {
+        const hipError_t e = hipFuncSetAttribute(f32_kernel(aggregate, wt), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_trace(const TraceParams &p, int fp64, int aggregate, int grid, int block, size_t lds,
                         hipStream_t s) {
     TraceParams q = p;
     void *args[] = {&q};
-    if (fp64) return hipLaunchKernel(f64_kernel(aggregate, weighted(p)), dim3(grid), dim3(block), args,
+    if (fp64) return hipLaunchKernel(f64_kernel(aggregate, weighting(p)), dim3(grid), dim3(block), args,
                                      sed_lds_bytes(p.K), s);
-    return hipLaunchKernel(f32_kernel(aggregate, weighted(p)), dim3(grid), dim3(block), args, lds, s);
+    return hipLaunchKernel(f32_kernel(aggregate, weighting(p)), dim3(grid), dim3(block), args, lds, s);
 }
 
 hipError_t launch_zero(double *A, int n, DevStats *st, int clear_counts, double *sed, int n_sed, hipStream_t s) {
@@ -989,15 +1069,15 @@ hipError_t launch_finalize(const FinalizeParams &p, hipStream_t s) {
 int trace_block_fp32() { return kBlockFP32; }
 
 hipError_t batch_configure(int aggregate, size_t lds) {
-    hipError_t e = hipFuncSetAttribute(batch_kernel(aggregate, false), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute(batch_kernel(aggregate, 0), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(batch_kernel(aggregate, true), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    return hipFuncSetAttribute(batch_kernel(aggregate, 1), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 hipError_t launch_trace_batch(const BatchParams &p, int aggregate, int grid, size_t lds, hipStream_t s) {
     BatchParams q = p;
     void *args[] = {&q};
-    return hipLaunchKernel(batch_kernel(aggregate, weighted(p)), dim3(grid), dim3(kBlockFP32), args, lds, s);
+    return hipLaunchKernel(batch_kernel(aggregate, weighting(p)), dim3(grid), dim3(kBlockFP32), args, lds, s);
 }
 
 hipError_t launch_zero_batch(double *A, size_t n_shells, DevStats *st, hipStream_t s) {

@@ -40,7 +40,8 @@ class Options(ct.Structure):
                 ("max_events", ct.c_uint64), ("stepping", ct.c_int32), ("max_lanes", ct.c_int32),
                 ("reemit_uniform", ct.c_int32), ("aggregate", ct.c_int32), ("batch", ct.c_int32),
                 ("use_g_E", ct.c_int32), ("g_E", ct.c_double), ("use_g_S", ct.c_int32), ("g_S", ct.c_double),
-                ("k_A", ct.c_double), ("k_S", ct.c_double)]
+                ("k_A", ct.c_double), ("k_S", ct.c_double), ("k_A_rho", ct.c_int32), ("k_A_lowest", ct.c_double),
+                ("k_A_highest", ct.c_double)]
 
 
 class Stats(ct.Structure):
@@ -317,7 +318,7 @@ class IREBatch:
         self.offsets = None
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.ire_batch_destroy(self._h)
             self._h = None
 

@@ -1,7 +1,7 @@
 """Noise of the temperature estimates under weighted sampling, on the synthetic
 clouds: the studies of Sect. 3.2 (Figs. 5 and 6: one weighting parameter of
-Table 1 at a time; Fig. 7: default, fixed k_A and FFI against the optical
-depth).
+Table 1 at a time; Fig. 7: default, fixed k_A, density-dependent k_A and FFI
+against the optical depth).
 
 For every setting, R independent GPU runs (seeds 1..R) of the same cloud give
 the relative scatter std(T)/mean(T) at the surface shell, the shell holding
@@ -94,8 +94,8 @@ def main(argv=None) -> int:
     # default, fixed k_A = 2.5 and FFI against the optical depth (externally heated)
     for tau in (0.1, 0.3, 1.0, 3.0, 10.0):
         model = wl.external_sphere(n=101, tau_V=tau)
-        for name, opts in (("default", {}), ("k_A=2.5", dict(k_A=2.5)), ("FFI", dict(ffi=1)),
-                           ("FFI absorption depth", dict(ffi=2))):
+        for name, opts in (("default", {}), ("k_A=2.5", dict(k_A=2.5)), ("k_A(rho) 3 -> 1", dict(k_A_rho=1)),
+                           ("FFI", dict(ffi=1)), ("FFI absorption depth", dict(ffi=2))):
             emit(dict(study="optical_depth", tau_V=tau, method=name,
                       **noise(model, "n_ext", n_pkg, a.runs, opts)))
     if a.out:

@@ -67,6 +67,13 @@ SERIAL_CASES = [
     ("ext101_kA_kS", wl.cfg_external_large, dict(n_ext=600), dict(k_A=1.8, k_S=0.6)),
     ("central200_gE_kA", wl.cfg_central, dict(n_ps=150), dict(use_g_E=1, g_E=-0.3, k_A=0.7)),
     ("ext50_ffi_abs", wl.cfg_external_small, dict(n_ext=2000), dict(ffi=2)),
+    # absorption scaling by density (two columns per flight)
+    ("ext101_kArho", wl.cfg_external_large, dict(n_ext=600), dict(k_A_rho=1)),
+    ("central200_kArho_kS", wl.cfg_central, dict(n_ps=150), dict(k_A_rho=1, k_S=1.4)),
+    ("graded_gray_kArho", lambda: dict(wl.gray_model(10, 1.5, external=False, r_in=0.05 * wl.R_OUT),
+                                       albedo=np.full(8, 0.4)),
+     dict(n_ps=2000), dict(k_A_rho=1, k_A_lowest=0.6, k_A_highest=2.0)),
+    ("ext50_kArho_ffi", wl.cfg_external_small, dict(n_ext=1500), dict(k_A_rho=1, ffi=1)),
 ]
 
 
@@ -126,7 +133,7 @@ def test_parallel_central_ensemble(ire):
 
 
 @pytest.mark.parametrize("opts", [dict(use_g_E=1, g_E=0.4, use_g_S=1, g_S=0.5), dict(k_A=1.5, k_S=0.7),
-                                  dict(ffi=2, k_bg=0.3)])
+                                  dict(ffi=2, k_bg=0.3), dict(k_A_rho=1)])
 def test_parallel_weighted_against_oracle_ensemble(ire, opts):
     # the FP32 parallel path with weighted sampling against the oracle's
     # ensemble with the same weights (16 seeds x 1e5 packages)
@@ -231,7 +238,7 @@ def test_invalid_arguments_rejected(ire):
             h.run(0, 100, 1)           # no point source set
         assert e.value.code == ire.IRE_E_STATE
         for bad in (dict(k_bg=0.0), dict(k_A=0.0), dict(k_S=float("inf")), dict(use_g_E=1, g_E=1.0),
-                    dict(use_g_S=2), dict(ffi=3)):
+                    dict(use_g_S=2), dict(ffi=3), dict(k_A_rho=1, k_A=2.0), dict(k_A_rho=1, k_A_lowest=0.0)):
             with pytest.raises(ire.IREError) as e:
                 h.set_options(**bad)
             assert e.value.code == ire.IRE_E_INVALID, bad
