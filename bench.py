@@ -29,12 +29,12 @@ if ROOT not in sys.path:
 # VALU instructions one lane executes per event on the FP32 tracer's paths
 # (least-squares fit of SQ_INSTS_VALU over one-lane runs of six clouds;
 # profiles/valu_fit_one_lane_clouds.md holds the fit and its command).
-VALU_PER_EVENT = {"cross": 23.71, "launch": 356.06, "scat": 270.40, "abs": 377.08}
+VALU_PER_EVENT = {"cross": 23.87, "launch": 379.06, "scat": 295.52, "abs": 412.71}
 
 # HBM bytes per tracer launch from FETCH_SIZE and WRITE_SIZE, scaled by a
 # plain 1 GiB copy (profiles/ire_trace_f32_ext101_tauV10_1e8.md); valid for
 # the tracer as profiled and set to None whenever the kernel changes.
-TRAFFIC_BYTES = {"ext101_tauV10_1e8": 2.009e9}
+TRAFFIC_BYTES = {"ext101_tauV10_1e8": 2.003e9}
 
 # MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = VALU lane-instruction issue peak
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
@@ -145,7 +145,7 @@ def bench_surrogate(args) -> dict:
 
     env = os.environ.get
     n_train = int(env("IRE_SUR_TRAIN_MODELS", "200000"))
-    train_scale = float(env("IRE_SUR_TRAIN_SCALE", "0.3"))
+    train_scale = float(env("IRE_SUR_TRAIN_SCALE", "1.0"))
     fit_steps = int(env("IRE_SUR_STEPS", "30000"))
     n_eval = int(env("IRE_SUR_EVAL_MODELS", "1024"))
     ref_scale = float(env("IRE_SUR_REF_SCALE", "4.0"))
