@@ -97,7 +97,7 @@ def bench_batch(args) -> dict:
         b.run()
         st = b.results(allow_limit=True)["stats"]
         ms.append(st["ms_run"])
-        ev = st if ev is None else {k: ev[k] + st[k] for k in ("n_cross", "n_launch", "n_scat", "n_abs")}
+        ev = st if ev is None else {k: ev[k] + st[k] for k in ("n_cross", "n_launch", "n_scat", "n_abs", "n_pass")}
     t1 = time.perf_counter()
     b.close()
     # per-model launches of a sample of the same models (same budgets)
@@ -113,7 +113,7 @@ def bench_batch(args) -> dict:
         t_single += time.perf_counter() - ts
     single_models_per_s = len(sample) / t_single
     k_ms = sum(ms) / len(ms)
-    per_launch = {k: ev[k] / args.steps for k in ("n_cross", "n_launch", "n_scat", "n_abs")}
+    per_launch = {k: ev[k] / args.steps for k in ("n_cross", "n_launch", "n_scat", "n_abs", "n_pass")}
     achieved = algorithmic_ops(per_launch) / (k_ms * 1e-3) / 1e12
     value = 4096 * args.steps / (t1 - t0)
     return {
@@ -309,9 +309,25 @@ def main() -> int:
         step(1 + s)
         st = h.stats()           # synchronises; tracing-kernel time from HIP events on `stream`
         kernel_ms.append(st["ms_trace"])
-        events = st if events is None else {k: events[k] + st[k] for k in ("n_cross", "n_launch", "n_scat", "n_abs")}
+        events = st if events is None else {k: events[k] + st[k] for k in ("n_cross", "n_launch", "n_scat", "n_abs", "n_pass")}
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+
+    # the optional weightings of the same cloud (reported, not the value): centre-weighted
+    # background directions (Eq. 5, k_bg = 0.2) and the forced first interaction (Eqs. 9-12);
+    # and eight independent accumulator groups instead of one running total per shell
+    variants = {}
+    for vname, vopt in (("k_bg=0.2", dict(k_bg=0.2)), ("ffi", dict(ffi=1)), ("k_bg=0.2+ffi", dict(k_bg=0.2, ffi=1)),
+                        ("replicas=8", dict(replicas=8))):
+        h.set_options(batch=int(os.environ.get("IRE_BENCH_BATCH", "0")),
+                      aggregate=int(os.environ.get("IRE_BENCH_AGG", "1")), **vopt)
+        ms = []
+        for s in range(2):
+            step(20_000 + s)
+            ms.append(h.stats()["ms_trace"])
+        variants[vname] = {"kernel_ms": ms[-1], "kernel_packages_per_s": n_pkg / (ms[-1] * 1e-3),
+                           "T_center_K": float(T[0].item())}
+    h.set_options(batch=int(os.environ.get("IRE_BENCH_BATCH", "0")), aggregate=int(os.environ.get("IRE_BENCH_AGG", "1")))
 
     # PCIe-inclusive rate: host model in, host results out (reported, not the value)
     tp0 = time.perf_counter()
@@ -323,7 +339,7 @@ def main() -> int:
     ms_step = (t1 - t0) * 1e3 / args.steps
     value = n_pkg * args.steps / (t1 - t0)
     k_ms = sum(kernel_ms) / len(kernel_ms)
-    per_launch = {k: events[k] / args.steps for k in ("n_cross", "n_launch", "n_scat", "n_abs")}
+    per_launch = {k: events[k] / args.steps for k in ("n_cross", "n_launch", "n_scat", "n_abs", "n_pass")}
     ops = algorithmic_ops(per_launch)
     achieved = ops / (k_ms * 1e-3) / 1e12
     line = {
@@ -345,6 +361,7 @@ def main() -> int:
         "kernel_packages_per_s": n_pkg / (k_ms * 1e-3),
         "events_per_launch": per_launch,
         "pcie_inclusive_packages_per_s": n_pkg / (tp1 - tp0),
+        "variants": variants,
         "T_center_K": float(host_res["T"][0]),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
                      "unit": "TOP/s (VALU lane-instructions)", "frac": achieved / VALU_PEAK_TOPS,

@@ -71,6 +71,15 @@ typedef struct ire_options {
                              density, k_A_highest at its highest (k_A must be 1); the weight is the fired
                              clock's 1/k times e^{modified - true absorption depth} */
     double k_A_lowest, k_A_highest;
+    int32_t replicas;     /* 1 (default): one running total of absorbed energy per shell for the whole device,
+                             as the single set of absorption counters of Sect. 2.3.  R = 2..8: the workgroups
+                             form R groups, each an independent IRE run over its share of the packages with
+                             its own accumulators (temperatures and re-emission slices from R times its own
+                             running total); the results are the sum over the groups.  This spreads the
+                             returning atomics over R addresses per shell (R = 8: about one group per XCD);
+                             it estimates the temperatures as the mean of R runs of N/R packages does, with
+                             the low-N bias of runs of N/R packages in the innermost cells (Sect. 3.1 finds
+                             ~1e8 packages per run enough for ~1 % in every cell).  Needs max_lanes = 0. */
 } ire_options;
 
 typedef struct ire_stats {
@@ -81,12 +90,14 @@ typedef struct ire_stats {
     uint64_t n_launch, n_cross, n_scat, n_abs, n_escape, n_direct, n_limit, n_floor;
     uint64_t n_below, n_above; /* final temperatures clamped to [t_min, t_max] */
     uint64_t n_reemit_above;   /* re-emission draws above the last temperature table point */
+    uint64_t n_pass;           /* event passes of the tracer's waves (each handles the interactions,
+                                  escapes and launches of the wave's parked lanes together) */
     float ms_tables, ms_trace, ms_finalize; /* host table build, tracing kernel, finalize kernel */
 } ire_stats;
 
 /* Fill *o with the defaults: k_bg 0.5, ffi 0, w_floor 1e-10, max_events 1e6,
  * stepping IRE_FP32, max_lanes 0, reemit_uniform 0, aggregate 1, batch 0,
- * use_g_E 0, g_E 0, use_g_S 0, g_S 0, k_A 1, k_S 1, k_A_rho 0, k_A_lowest 3, k_A_highest 1. */
+ * use_g_E 0, g_E 0, use_g_S 0, g_S 0, k_A 1, k_S 1, k_A_rho 0, k_A_lowest 3, k_A_highest 1, replicas 1. */
 int ire_default_options(ire_options *o);
 
 /* Create a handle bound to HIP device `hip_device`; *out is owned by the caller
@@ -210,6 +221,7 @@ typedef struct ire_batch_stats {
     double escaped, ffi_escaped, terminated;
     uint64_t n_launch, n_cross, n_scat, n_abs, n_escape, n_limit, n_floor, n_below, n_above;
     uint64_t n_models, n_items, n_shells;
+    uint64_t n_pass;           /* event passes of the tracer's waves */
     float ms_run;              /* zero + trace + finalize on the device (HIP events) */
 } ire_batch_stats;
 

@@ -726,12 +726,22 @@ static void trace_package(const ostate *s, tally_t *t, int src, uint64_t pid, ui
             if (events == 1 && t->first_abs) t->first_abs[i] += E;
             double A_before = acc_read(s, t, i);
             acc_add(s, t, i, E);
+            /* Random numbers: one block (slice position, frequency, direction, tau_A,
+             * tau_S); a second block when the slice position is needed or the
+             * position in the shell is redrawn. */
+            int straddle = 0;
             next_block(&rs, u);
-            next_block(&rs, u2);
             if (s->o.table_mode) {
-                double astar = (A_before + u[0] * E) / s->M[i];
-                int j = bin_below(s->G, m->n_t, astar);
-                int row = j + 1;
+                /* the bin of a* uniform in [A_before, A_before + E] / M_i (reading R8): a
+                 * slice inside one bin fixes the bin without a draw; one that reaches
+                 * across a bin edge takes a* from u[0] and tau_S from the second block */
+                const double alo = A_before / s->M[i], ahi = (A_before + E) / s->M[i];
+                int row = bin_below(s->G, m->n_t, alo) + 1;
+                straddle = row < m->n_t && s->G[row] <= ahi;
+                if (straddle) {
+                    next_block(&rs, u2);
+                    row = bin_below(s->G, m->n_t, (A_before + u[0] * E) / s->M[i]) + 1;
+                }
                 if (row > m->n_t - 1) { row = m->n_t - 1; t->st.n_reemit_above++; }
                 k = sample_cdf(s->D + (size_t)row * K, K, u[1]);
             } else {
@@ -764,6 +774,7 @@ static void trace_package(const ostate *s, tally_t *t, int src, uint64_t pid, ui
             if (r > 0.0) { for (int j = 0; j < 3; ++j) xh[j] = x[j] / r; }
             else { xh[0] = 0; xh[1] = 0; xh[2] = 1; }
             if (s->o.reemit_uniform) {
+                if (!straddle) next_block(&rs, u2);
                 double r0 = s->R[i], r1 = s->R[i + 1];
                 double rn = cbrt(r0 * r0 * r0 + u2[1] * (r1 * r1 * r1 - r0 * r0 * r0));
                 for (int j = 0; j < 3; ++j) x[j] = rn * xh[j];
@@ -780,7 +791,7 @@ static void trace_package(const ostate *s, tally_t *t, int src, uint64_t pid, ui
             double sn = sqrt(fmax(0.0, 1.0 - mu * mu));
             for (int j = 0; j < 3; ++j) d[j] = mu * xh[j] + sn * e[j];
             tauA = -log(u[3]);
-            tauS = -log(u2[0]) / kS;
+            tauS = -log(straddle ? u2[0] : u[0]) / kS;
             kw = s->kscale;
             tA0 = tauA;
             tS0 = tauS;

@@ -55,6 +55,7 @@ struct ire_model {
     DevBuf<double> sed;               // 4*K escaping spectrum (total, then unscattered)
     // run state
     bool begun = false;
+    int replicas = 1;                 // accumulator groups of the current run
     unsigned long long n_total[2] = {0, 0};
     unsigned long long n_done[2] = {0, 0};
     unsigned long long seed = 0;
@@ -133,7 +134,7 @@ int build_tables(ire_model *m) {
         (e = m->rkf.upload(rkf)) != hipSuccess || (e = m->rkd.upload(rkd)) != hipSuccess)
         return e == hipErrorOutOfMemory ? m->fail(IRE_E_NOMEM, "device allocation failed")
                                         : m->hip_fail(e, "table upload");
-    if ((e = m->A.ensure((size_t)n * ire::kAccStride)) != hipSuccess ||
+    if ((e = m->A.ensure((size_t)ire::kMaxReplicas * n * ire::kAccStride)) != hipSuccess ||
         (e = m->A_out.ensure(n)) != hipSuccess || (e = m->T_out.ensure(n)) != hipSuccess ||
         (e = m->stats.ensure(1)) != hipSuccess || (e = m->sed.ensure((size_t)4 * K)) != hipSuccess)
         return m->fail(IRE_E_NOMEM, "device allocation failed: %s", hipGetErrorString(e));
@@ -175,6 +176,7 @@ int ire_default_options(ire_options *o) {
     o->k_A_rho = 0;
     o->k_A_lowest = 3.0;
     o->k_A_highest = 1.0;
+    o->replicas = 1;
     return IRE_OK;
 }
 
@@ -328,6 +330,9 @@ int ire_set_options(ire_model *m, const ire_options *o) {
     if (o->reemit_uniform != 0 && o->reemit_uniform != 1) return m->fail(IRE_E_INVALID, "reemit_uniform must be 0 or 1");
     if (o->aggregate != 0 && o->aggregate != 1) return m->fail(IRE_E_INVALID, "aggregate must be 0 or 1");
     if (o->batch < 0 || o->batch > 64) return m->fail(IRE_E_INVALID, "batch must be in [0, 64]");
+    if (o->replicas < 1 || o->replicas > ire::kMaxReplicas)
+        return m->fail(IRE_E_INVALID, "replicas must be in [1, %d]", ire::kMaxReplicas);
+    if (o->replicas > 1 && o->max_lanes > 0) return m->fail(IRE_E_INVALID, "replicas > 1 needs max_lanes = 0");
     m->opt = *o;
     return IRE_OK;
 }
@@ -356,8 +361,9 @@ int ire_begin(ire_model *m, uint64_t n_ext_total, uint64_t n_ps_total, uint64_t 
     m->ms_trace = 0.0f;
     m->ms_finalize = 0.0f;
     m->timed = false;
-    if ((e = ire::launch_zero(m->A.p, (int)m->rho.size(), m->stats.p, 1, m->sed.p, 4 * (int)m->nu.size(), nullptr)) !=
-        hipSuccess)
+    m->replicas = m->opt.replicas;   // fixed for the run: every ire_advance of it uses the same groups
+    if ((e = ire::launch_zero(m->A.p, ire::kMaxReplicas * (int)m->rho.size(), m->stats.p, 1, m->sed.p,
+                              4 * (int)m->nu.size(), nullptr)) != hipSuccess)
         return m->hip_fail(e, "zero accumulators");
     if ((e = hipStreamSynchronize(nullptr)) != hipSuccess) return m->hip_fail(e, "zero accumulators");
     m->begun = true;
@@ -370,6 +376,8 @@ int ire_advance(ire_model *m, uint64_t n_ext, uint64_t n_ps, void *hip_stream) {
     if (n_ext > m->n_total[0] - m->n_done[0] || n_ps > m->n_total[1] - m->n_done[1])
         return m->fail(IRE_E_INVALID, "more packages requested than remain in the run");
     if (n_ext + n_ps == 0) return IRE_OK;
+    if (m->replicas > 1 && m->opt.max_lanes > 0)
+        return m->fail(IRE_E_STATE, "a run begun with replicas > 1 cannot continue with max_lanes > 0");
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
     hipError_t e;
     if ((e = hipSetDevice(m->device)) != hipSuccess) return m->hip_fail(e, "hipSetDevice");
@@ -415,6 +423,7 @@ int ire_advance(ire_model *m, uint64_t n_ext, uint64_t n_ps, void *hip_stream) {
     p.k_A = m->opt.k_A; p.k_S = m->opt.k_S;
     p.k_A_rho = m->opt.k_A_rho; p.rkf = m->rkf.p; p.rkd = m->rkd.p;
     p.A = m->A.p; p.stats = m->stats.p; p.sed = m->sed.p;
+    p.replicas = m->replicas;
     {
         const unsigned long long waves = (unsigned long long)grid * (block / 64);
         unsigned long long c = (n_ext + n_ps) / (waves * 8ull);
@@ -458,6 +467,7 @@ static int finalize(ire_model *m, hipStream_t s) {
     f.n = (int)m->rho.size();
     f.n_t = m->n_t;
     f.A = m->A.p; f.invM = m->invM.p; f.Gd = m->Gd.p; f.lnG = m->lnGd.p; f.lnT = m->lnTd.p;
+    f.replicas = m->replicas;
     f.t_min = m->t_min; f.t_max = m->t_max;
     f.A_out = m->A_out.p; f.T_out = m->T_out.p;
     f.stats = m->stats.p;
@@ -485,6 +495,7 @@ static void fill_stats(const ire_model *m, const ire::DevStats &hs, ire_stats *s
         stats->n_below = hs.cnt[ire::C_BELOW];
         stats->n_above = hs.cnt[ire::C_ABOVE];
         stats->n_reemit_above = hs.cnt[ire::C_REEMIT_ABOVE];
+        stats->n_pass = hs.cnt[ire::C_PASS];
         stats->ms_tables = m->ms_tables;
         stats->ms_trace = m->ms_trace;
         stats->ms_finalize = m->ms_finalize;
@@ -572,6 +583,7 @@ int ire_get_results_dev(ire_model *m, double *absorbed_dev, double *T_dev, void 
     f.n = (int)m->rho.size();
     f.n_t = m->n_t;
     f.A = m->A.p; f.invM = m->invM.p; f.Gd = m->Gd.p; f.lnG = m->lnGd.p; f.lnT = m->lnTd.p;
+    f.replicas = m->replicas;
     f.t_min = m->t_min; f.t_max = m->t_max;
     f.A_out = absorbed_dev ? absorbed_dev : m->A_out.p;
     f.T_out = T_dev ? T_dev : m->T_out.p;

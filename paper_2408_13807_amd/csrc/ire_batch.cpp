@@ -83,7 +83,7 @@ namespace {
 
 size_t lds_bytes(const ire_batch *b) {
     const int K = (int)b->nu.size();
-    return (size_t)b->max_table * sizeof(ire::ShellF) + (size_t)K * sizeof(ire::DustF) +
+    return (size_t)(b->max_table + ire::kPadBelow) * sizeof(ire::ShellF) + (size_t)K * sizeof(ire::DustF) +
            (size_t)2 * K * sizeof(float) + (size_t)b->n_t * sizeof(float) + (size_t)b->n_t * K * sizeof(float) +
            ire::guide_bytes(b->n_t);
 }
@@ -516,6 +516,7 @@ int ire_batch_get(ire_batch *b, double *A_flat, double *T_flat, ire_batch_stats 
         st->n_floor = hs.cnt[ire::C_FLOOR];
         st->n_below = hs.cnt[ire::C_BELOW];
         st->n_above = hs.cnt[ire::C_ABOVE];
+        st->n_pass = hs.cnt[ire::C_PASS];
         st->n_models = b->models.size();
         st->n_items = b->items.size();
         st->n_shells = b->n_shells;

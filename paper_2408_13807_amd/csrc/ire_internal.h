@@ -13,6 +13,12 @@ constexpr int kAccStride = 16;
 // density): a flight that leaves the cloud ends in the first; the second keeps
 // the tracer's one-record-ahead reads inside the table for every lane.
 constexpr int kSentinels = 2;
+// The FP32 kernels stage the table in LDS behind one pad record: a lane that is
+// not in flight keeps stepping with a stale record, and its reads then stay
+// within one record of its shell, so inside [pad, second sentinel].
+constexpr int kPadBelow = 1;
+// Largest number of independent accumulator groups of a single-model run.
+constexpr int kMaxReplicas = 8;
 // Guide tables (cut-point method, Chen & Asau 1974) accelerate the searches
 // of the G(T) table and of the frequency CDFs; the searches stay exact (a
 // bidirectional scan from the guide's start).  Layout of the guide bytes:
@@ -37,7 +43,7 @@ struct DustD { double kA, kS, inv_kA, inv_kS, g, alb, kext, pad; };
 
 enum Counter {
     C_LAUNCH, C_CROSS, C_SCAT, C_ABS, C_ESCAPE, C_DIRECT, C_LIMIT, C_FLOOR,
-    C_REEMIT_ABOVE, C_BELOW, C_ABOVE, C_COUNT
+    C_REEMIT_ABOVE, C_BELOW, C_ABOVE, C_PASS, C_COUNT
 };
 enum Tally { T_ESC_EXT, T_ESC_PS, T_FFI, T_TERM, T_COUNT };
 
@@ -81,6 +87,7 @@ struct TraceParams {
     const float2 *rkf;                // cavity + n + kSentinels records (table units), FP32 path
     const double2 *rkd;               // the same, FP64 path
     int max_lanes;                    // 0 = no limit
+    int replicas;                     // accumulator groups: workgroup b adds into copy b % replicas
     unsigned long long chunk;         // package indices a wave takes from the cursor at once (>= 64)
     int batch;                        // parked lanes that trigger an event pass (1..64)
     double *A;                        // n accumulators, stride kAccStride
@@ -90,7 +97,8 @@ struct TraceParams {
 
 struct FinalizeParams {
     int n, n_t;
-    const double *A;                  // stride kAccStride
+    const double *A;                  // stride kAccStride; `replicas` copies of n, summed
+    int replicas;
     const double *invM;
     const double *Gd, *lnG, *lnT;
     double t_min, t_max;

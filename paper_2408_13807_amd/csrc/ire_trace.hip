@@ -36,6 +36,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 #include "ire_internal.h"
 
@@ -87,10 +88,14 @@ template <> struct P<float> {
         return u < 0x1.fffffep-1f ? u : 0x1.fffffep-1f;
     }
     static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
-    static __device__ __forceinline__ float nlog(float u) { return -__logf(u); }
+    // u is a normal number in (0, 1): the hardware log2 needs no range reduction
+    static __device__ __forceinline__ float nlog(float u) { return -0x1.62e430p-1f * __builtin_amdgcn_logf(u); }
     static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
     static __device__ __forceinline__ float cos2pi(float u) { return __builtin_amdgcn_cosf(u); }
-    static __device__ __forceinline__ float powr(float a, float b) { return __powf(a, b); }
+    // a in (0, 1]: 2^(b log2 a) with the hardware log2 and exp2
+    static __device__ __forceinline__ float powr(float a, float b) {
+        return __builtin_amdgcn_exp2f(b * __builtin_amdgcn_logf(a));
+    }
     static __device__ __forceinline__ float expm1_(float x) { return expm1f(x); }
     static __device__ __forceinline__ float log1p_(float x) { return log1pf(x); }
     static __device__ __forceinline__ float cbrt_(float x) { return cbrtf(x); }
@@ -254,8 +259,12 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
 
 // Per-lane event counters and energy tallies (flushed once per wave).
 struct LaneCounters {
-    uint32_t launch = 0, cross = 0, scat = 0, abs = 0, escape = 0, direct = 0, limit = 0, floor = 0,
+    uint32_t launch = 0, sent = 0, scat = 0, abs = 0, escape = 0, direct = 0, limit = 0, floor = 0,
              reabove = 0;
+    // steps that moved a package, counted per wave (the same value in every
+    // lane); the crossings are these less the steps into the sentinel (`sent`)
+    unsigned long long steps = 0;
+    uint32_t passes = 0;           // event passes of this wave (the same value in every lane)
     double esc0 = 0.0, esc1 = 0.0, ffi = 0.0, term = 0.0;
 };
 
@@ -266,6 +275,7 @@ struct ModelCtx {
     int n, cav;
     const double *invM;              // n: 1 / shell mass
     double *A;                       // n absorbed-energy accumulators, stride kAccStride
+    double a_scale;                  // running total -> whole-run estimate (the number of groups)
     double eps[2];                   // package energy per source
     unsigned long long n_ext, n_ps;  // packages to trace per source
     unsigned long long pid0[2];      // first package id per source
@@ -359,9 +369,16 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
     // its tangent point inside the inner sphere, outward otherwise), so its
     // record is requested first and its LDS latency overlaps the arithmetic.
     // A package that does not cross parks with t and sig unchanged; the event
-    // pass moves it to the interaction point.
+    // pass moves it to the interaction point.  `fly` marks the packages in
+    // flight during a crossing sweep, held as the wave's lane mask.
+    // In the FP32 kernels the record of the shell just entered replaces the
+    // current one in every lane: a lane that did not move stops flying, and
+    // the event pass reloads its record from `ps`; the LDS pad record below
+    // the table keeps such a lane's stale reads in bounds.
+    unsigned long long fly = 0;    // wave-uniform
+    uint32_t sweep_steps = 0;      // moving steps of the current sweep (a sweep ends before 2^32)
+    constexpr bool kLoose = std::is_same<R, float>::value;
     auto step = [&]() {
-        const bool f = st == ST_FLY;
         const bool inward = (t < (R)0) && (b2 < cur.r2_in);
         const Shell *const pn = inward ? ps - 1 : ps + 1;
         const Shell nx = P<R>::shell(pn);
@@ -377,7 +394,10 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
             dsA = curk.x * (tn - t);
             cross = cross && dsA < sigA;
         }
-        const bool mv = f && cross;
+        // the lanes that cross, as a mask first (a compare's mask needs no
+        // per-lane boolean), then as the per-lane condition of the selects
+        fly &= __ballot(cross);
+        const bool mv = __builtin_amdgcn_inverse_ballot_w64(fly);
         sig = mv ? sig - ds : sig;
         if constexpr (KRHO) {
             sigA = mv ? sigA - dsA : sigA;
@@ -385,18 +405,22 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
         }
         t = mv ? tn : t;
         ps = mv ? pn : ps;
-        lc.cross += mv ? 1u : 0u;
-        st = (f && !cross) ? (int)ST_EVT : st;
+        sweep_steps += (uint32_t)__popcll(fly);
         // keep the compiler from hoisting the use of the record (and with it
         // the wait for its LDS read) above the step's arithmetic
         __builtin_amdgcn_sched_barrier(0);
-        cur.r2_in = mv ? nx.r2_in : cur.r2_in;
-        cur.r2_out = mv ? nx.r2_out : cur.r2_out;
-        cur.rho = mv ? nx.rho : cur.rho;
-        cur.inv_rho = mv ? nx.inv_rho : cur.inv_rho;
-        if constexpr (KRHO) {
-            curk.x = mv ? nxk.x : curk.x;
-            curk.y = mv ? nxk.y : curk.y;
+        if constexpr (kLoose) {
+            cur = nx;
+            if constexpr (KRHO) curk = nxk;
+        } else {
+            cur.r2_in = mv ? nx.r2_in : cur.r2_in;
+            cur.r2_out = mv ? nx.r2_out : cur.r2_out;
+            cur.rho = mv ? nx.rho : cur.rho;
+            cur.inv_rho = mv ? nx.inv_rho : cur.inv_rho;
+            if constexpr (KRHO) {
+                curk.x = mv ? nxk.x : curk.x;
+                curk.y = mv ? nxk.y : curk.y;
+            }
         }
     };
 
@@ -405,6 +429,10 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
     // re-emission, then new free paths.
     auto event_pass = [&]() {
             // ---- event batch
+            if constexpr (kLoose) {
+                cur = P<R>::shell(ps);
+                if constexpr (KRHO) curk = rk[ps - sh];
+            }
             const int i = (int)(ps - sh);        // internal shell index
             bool absorbing = false, scattering = false;
             // a parked package still stands where its last step began: move it
@@ -455,7 +483,7 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
                         if (events == 0) atomicAdd(&sed[2 * K + src * K + k], e);
                     }
                     lc.escape++;
-                    lc.cross--;
+                    lc.sent++;
                     if (events == 0) lc.direct++;
                     st = ST_DEAD;
                 } else if (events >= o.max_events) {
@@ -511,22 +539,34 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
             // absorption: deposit E into the shell; A_before locates this package's
             // slice [A_before, A_before + E] of the shell's absorbed power
             const double E = absorbing ? eps * (double)W : 0.0;
-            const double invM = absorbing ? mc.invM[i - cav] : 0.0;   // issued before the atomic's round trip
+            const double invM = absorbing ? mc.a_scale * mc.invM[i - cav] : 0.0;   // issued before the atomic's round trip
             double A_before = 0.0;
             if (__ballot(absorbing)) A_before = fetch_add_energy<AGG>(mc.A, i - cav, E, absorbing);
 
             Rand4 r1{0, 0, 0, 0}, r2b{0, 0, 0, 0};
             if (ev) r1 = philox(blk++, pid_lo, pid_hi, (uint32_t)src, key0, key1);
-            if (absorbing) r2b = philox(blk++, pid_lo, pid_hi, (uint32_t)src, key0, key1);
 
-            // new frequency: source spectrum at launch, difference spectrum at re-emission
+            // re-emission: a* uniform in the package's slice [A_before, A_before + E] / M
+            // selects the G(T) bin whose difference spectrum is drawn.  A slice almost
+            // never reaches across a bin edge (it is ~1e-6 of the shell's total), and
+            // then the bin does not depend on a*: its uniform is drawn only for a slice
+            // that does, so the first Philox block usually covers all five draws
             int row = 0;
+            bool straddle = false;
             if (absorbing) {
-                const double astar = (A_before + (((double)r1.x + 0.5) * 0x1p-32) * E) * invM;
-                const R a = (R)astar;
-                row = count_le_from(G, n_t, a, g_guide(gguide, n_t, g_lg0, g_scale, (float)a));
-                if (row > n_t - 1) { row = n_t - 1; lc.reabove++; }
+                const R alo = (R)(A_before * invM), ahi = (R)((A_before + E) * invM);
+                row = count_le_from(G, n_t, alo, g_guide(gguide, n_t, g_lg0, g_scale, (float)alo));
+                straddle = row < n_t && G[row] <= ahi;
                 lc.abs++;
+            }
+            if ((absorbing && straddle) || (absorbing && o.reemit_uniform))
+                r2b = philox(blk++, pid_lo, pid_hi, (uint32_t)src, key0, key1);
+            if (absorbing) {
+                if (straddle) {
+                    const double astar = (A_before + (((double)r1.x + 0.5) * 0x1p-32) * E) * invM;
+                    row = count_le_from(G, n_t, (R)astar, row);
+                }
+                if (row > n_t - 1) { row = n_t - 1; lc.reabove++; }
             }
             if (launching || absorbing) {
                 const R *tab = launching ? cdf + src * K : D + (size_t)row * K;
@@ -592,7 +632,7 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
             // both free paths are redrawn after every event (Eq. 1), from
             // k e^{-k tau} when scaled (Eq. 8)
             R tauA = P<R>::nlog(P<R>::uni(absorbing ? r1.w : r1.z)) * inv_kA;
-            R tauS = P<R>::nlog(P<R>::uni(absorbing ? r2b.x : r1.w)) * inv_kS;
+            R tauS = P<R>::nlog(P<R>::uni(absorbing ? (straddle ? r2b.x : r1.x) : r1.w)) * inv_kS;
             bool kw_new = kscale;
 
             // launch geometry and launch weights (Eqs. 2-3, Eq. 5, Eqs. 9-12)
@@ -605,8 +645,9 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
                         mu = P<R>::sqrt_(u1);
                     } else {
                         const R kb = (R)o.k_bg;
+                        // mu^(2 - 1/k) = mu^2 / u since mu^(1/k) = u
                         mu = P<R>::powr(u1, kb);
-                        W = (R)2 * kb * P<R>::powr(mu, (R)2 - (R)1 / kb);
+                        W = (R)2 * kb * mu * mu * P<R>::rcp(u1);
                     }
                     ps = sentinel - 1;
                     t = -mu;
@@ -705,19 +746,24 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
             const int live = __popcll(__ballot(st != ST_DONE));
             const int half = (live + 1) / 2;
             const int want = batch < half ? batch : (half > 0 ? half : 1);
+            fly = __ballot(st == ST_FLY);
+            sweep_steps = 0;
             for (;;) {
-                const int nfly = __popcll(__ballot(st == ST_FLY));
+                const int nfly = __popcll(fly);
                 if (nfly == 0 || live - nfly >= want) break;
                 step();
                 step();
                 step();
                 step();
             }
+            st = (st == ST_FLY && !__builtin_amdgcn_inverse_ballot_w64(fly)) ? (int)ST_EVT : st;
+            lc.steps += sweep_steps;
         }
         // nothing in flight, nothing parked: all packages done
         if (__ballot(st != ST_DONE && st != ST_FLY) == 0) break;
 
         // ---- event batch
+        lc.passes++;
         event_pass();
         cur = P<R>::shell(ps);
         if constexpr (KRHO) curk = rk[ps - sh];
@@ -727,11 +773,15 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
 // Sum the per-lane counters over the wave and add them to the launch statistics.
 __device__ __forceinline__ void flush_counters(const LaneCounters &lc, DevStats *stats) {
     const int lane = __lane_id();
-    const unsigned long long cs[9] = {lc.launch, lc.cross, lc.scat, lc.abs, lc.escape,
-                                      lc.direct, lc.limit, lc.floor, lc.reabove};
-    const int cidx[9] = {C_LAUNCH, C_CROSS, C_SCAT, C_ABS, C_ESCAPE, C_DIRECT, C_LIMIT, C_FLOOR, C_REEMIT_ABOVE};
+    // modular: the wave's sum is the number of crossings
+    const unsigned long long cross = (lane == 0 ? lc.steps : 0ull) - (unsigned long long)lc.sent;
+    const unsigned long long cs[10] = {lc.launch, cross, lc.scat, lc.abs, lc.escape,
+                                       lc.direct, lc.limit, lc.floor, lc.reabove,
+                                       lane == 0 ? (unsigned long long)lc.passes : 0ull};
+    const int cidx[10] = {C_LAUNCH, C_CROSS, C_SCAT, C_ABS, C_ESCAPE, C_DIRECT, C_LIMIT, C_FLOOR, C_REEMIT_ABOVE,
+                          C_PASS};
 #pragma unroll
-    for (int j = 0; j < 9; ++j) {
+    for (int j = 0; j < 10; ++j) {
         const unsigned long long v = wave_sum_u64(cs[j]);
         if (lane == 0 && v) atomicAdd(&stats->cnt[cidx[j]], v);
     }
@@ -757,7 +807,11 @@ __device__ __forceinline__ void single_model(const TraceParams &p, const typenam
     mc.n = p.n;
     mc.cav = p.cavity;
     mc.invM = p.invM;
-    mc.A = p.A;
+    // accumulator group of this workgroup: an independent run over the packages its
+    // waves take, whose running total times the number of groups estimates the whole
+    const int rep = p.replicas > 1 ? (int)(blockIdx.x % (unsigned)p.replicas) : 0;
+    mc.A = p.A + (size_t)rep * p.n * kAccStride;
+    mc.a_scale = p.replicas > 1 ? (double)p.replicas : 1.0;
     mc.eps[0] = p.eps[0];
     mc.eps[1] = p.eps[1];
     mc.n_ext = p.n_ext;
@@ -783,13 +837,13 @@ template <bool AGG, int WT>
 __global__ __launch_bounds__(kBlockFP32) void ire_trace_f32(TraceParams p) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int nsh = p.n + p.cavity + kSentinels, K = p.K, n_t = p.n_t;
-    ShellF *s_sh = reinterpret_cast<ShellF *>(smem);
+    ShellF *s_sh = reinterpret_cast<ShellF *>(smem) + kPadBelow;
     DustF *s_dust = reinterpret_cast<DustF *>(s_sh + nsh);
     float *s_cdf = reinterpret_cast<float *>(s_dust + K);
     float *s_G = s_cdf + 2 * K;
     float *s_D = s_G + n_t;
     uint32_t *s_guide = reinterpret_cast<uint32_t *>(s_D + (size_t)n_t * K);
-    for (int j = threadIdx.x; j < nsh; j += blockDim.x) s_sh[j] = p.shf[j];
+    for (int j = threadIdx.x - kPadBelow; j < nsh; j += blockDim.x) s_sh[j] = j < 0 ? ShellF{0, 0, 0, 0} : p.shf[j];
     for (int j = threadIdx.x; j < K; j += blockDim.x) s_dust[j] = p.dustf[j];
     for (int j = threadIdx.x; j < 2 * K; j += blockDim.x) s_cdf[j] = p.cdff[j];
     for (int j = threadIdx.x; j < n_t; j += blockDim.x) s_G[j] = p.Gf[j];
@@ -799,9 +853,9 @@ __global__ __launch_bounds__(kBlockFP32) void ire_trace_f32(TraceParams p) {
     for (int j = threadIdx.x; j < ng; j += blockDim.x) s_guide[j] = reinterpret_cast<const uint32_t *>(p.guide)[j];
     double *s_sed = reinterpret_cast<double *>(s_guide + ng);
     for (int j = threadIdx.x; j < 4 * K; j += blockDim.x) s_sed[j] = 0.0;
-    float2 *s_rk = reinterpret_cast<float2 *>(s_sed + 4 * K);
+    float2 *s_rk = reinterpret_cast<float2 *>(s_sed + 4 * K) + kPadBelow;
     if constexpr (WT == 2)
-        for (int j = threadIdx.x; j < nsh; j += blockDim.x) s_rk[j] = p.rkf[j];
+        for (int j = threadIdx.x - kPadBelow; j < nsh; j += blockDim.x) s_rk[j] = j < 0 ? float2{0, 0} : p.rkf[j];
     __syncthreads();
     ModelCtx<float> mc;
     MethodOpts o;
@@ -855,7 +909,8 @@ __global__ void ire_cursor_reset(DevStats *st) {
 __global__ void ire_finalize(FinalizeParams p) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= p.n) return;
-    const double A = p.A[(size_t)i * kAccStride];
+    double A = 0.0;
+    for (int r = 0; r < p.replicas; ++r) A += p.A[((size_t)r * p.n + i) * kAccStride];
     const double a = A * p.invM[i];
     double T;
     if (!(a >= p.Gd[0])) {
@@ -886,8 +941,9 @@ __global__ __launch_bounds__(kBlockFP32) void ire_trace_batch(BatchParams p) {
     __shared__ unsigned long long s_item;
     __shared__ unsigned long long s_cursor;
     const int K = p.K, n_t = p.n_t;
-    ShellF *s_sh = reinterpret_cast<ShellF *>(smem);
+    ShellF *s_sh = reinterpret_cast<ShellF *>(smem) + kPadBelow;
     DustF *s_dust = reinterpret_cast<DustF *>(s_sh + p.max_table);
+    if (threadIdx.x == 0) s_sh[-1] = ShellF{0, 0, 0, 0};
     float *s_cdf = reinterpret_cast<float *>(s_dust + K);
     float *s_G = s_cdf + 2 * K;
     float *s_D = s_G + n_t;
@@ -934,6 +990,7 @@ __global__ __launch_bounds__(kBlockFP32) void ire_trace_batch(BatchParams p) {
         mc.cav = bm.cav;
         mc.invM = p.invM + bm.acc_off;
         mc.A = p.A + (size_t)bm.acc_off * kAccStride;
+        mc.a_scale = 1.0;
         mc.eps[0] = bm.eps;
         mc.eps[1] = bm.eps;
         mc.n_ext = bm.src == 0 ? item.count : 0;
@@ -985,9 +1042,9 @@ __global__ void ire_finalize_batch(BatchFinalizeParams p) {
 }  // namespace
 
 size_t trace_lds_bytes(int n_table, int K, int n_t) {
-    return (size_t)n_table * sizeof(ShellF) + (size_t)K * sizeof(DustF) + (size_t)2 * K * sizeof(float) +
-           (size_t)n_t * sizeof(float) + (size_t)n_t * K * sizeof(float) + guide_bytes(n_t) + sed_lds_bytes(K) +
-           (size_t)n_table * sizeof(float2);
+    return (size_t)(n_table + kPadBelow) * sizeof(ShellF) + (size_t)K * sizeof(DustF) +
+           (size_t)2 * K * sizeof(float) + (size_t)n_t * sizeof(float) + (size_t)n_t * K * sizeof(float) +
+           guide_bytes(n_t) + sed_lds_bytes(K) + (size_t)(n_table + kPadBelow) * sizeof(float2);
 }
 
 size_t sed_lds_bytes(int K) { return (size_t)4 * K * sizeof(double); }

@@ -41,14 +41,14 @@ class Options(ct.Structure):
                 ("reemit_uniform", ct.c_int32), ("aggregate", ct.c_int32), ("batch", ct.c_int32),
                 ("use_g_E", ct.c_int32), ("g_E", ct.c_double), ("use_g_S", ct.c_int32), ("g_S", ct.c_double),
                 ("k_A", ct.c_double), ("k_S", ct.c_double), ("k_A_rho", ct.c_int32), ("k_A_lowest", ct.c_double),
-                ("k_A_highest", ct.c_double)]
+                ("k_A_highest", ct.c_double), ("replicas", ct.c_int32)]
 
 
 class Stats(ct.Structure):
     _fields_ = [("L_ext", ct.c_double), ("L_ps", ct.c_double), ("escaped", ct.c_double * 2),
                 ("ffi_escaped", ct.c_double), ("terminated", ct.c_double)] + [
         (f, ct.c_uint64) for f in ("n_launch", "n_cross", "n_scat", "n_abs", "n_escape", "n_direct",
-                                   "n_limit", "n_floor", "n_below", "n_above", "n_reemit_above")] + [
+                                   "n_limit", "n_floor", "n_below", "n_above", "n_reemit_above", "n_pass")] + [
         ("ms_tables", ct.c_float), ("ms_trace", ct.c_float), ("ms_finalize", ct.c_float)]
 
 
@@ -75,7 +75,7 @@ class BatchStats(ct.Structure):
     _fields_ = [("L_total", ct.c_double), ("escaped", ct.c_double), ("ffi_escaped", ct.c_double),
                 ("terminated", ct.c_double)] + [
         (f, ct.c_uint64) for f in ("n_launch", "n_cross", "n_scat", "n_abs", "n_escape", "n_limit", "n_floor",
-                                   "n_below", "n_above", "n_models", "n_items", "n_shells")] + [
+                                   "n_below", "n_above", "n_models", "n_items", "n_shells", "n_pass")] + [
         ("ms_run", ct.c_float)]
 
 

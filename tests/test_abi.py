@@ -33,7 +33,7 @@ def test_options_layout_and_defaults():
     assert (o.k_bg, o.ffi, o.w_floor, o.max_events, o.stepping, o.max_lanes, o.reemit_uniform,
             o.aggregate, o.batch) == (0.5, 0, 1e-10, 1000000, 0, 0, 0, 1, 0)
     assert (o.use_g_E, o.g_E, o.use_g_S, o.g_S, o.k_A, o.k_S) == (0, 0.0, 0, 0.0, 1.0, 1.0)
-    assert (o.k_A_rho, o.k_A_lowest, o.k_A_highest) == (0, 3.0, 1.0)
+    assert (o.k_A_rho, o.k_A_lowest, o.k_A_highest, o.replicas) == (0, 3.0, 1.0, 1)
     b = ire.default_batch_options()
     assert (b.use_g_E, b.g_E, b.use_g_S, b.g_S, b.k_A, b.k_S, b.use_graph) == (0, 0.0, 0, 0.0, 1.0, 1.0, 1)
 
@@ -64,3 +64,29 @@ def test_null_handle_calls_are_safe():
     assert lib.ire_set_options(None, None) == ire.IRE_E_INVALID
     assert lib.ire_run(None, 1, 0, 1, None) == ire.IRE_E_INVALID
     assert lib.ire_last_error(None) == b"null handle"
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors of the header's structs have the C compiler's field
+    offsets and sizes (a field added on one side only fails here)."""
+    from paper_2408_13807_amd import ire, surrogate
+    pairs = [("ire_options", ire.Options), ("ire_stats", ire.Stats), ("ire_model_desc", ire.ModelDesc),
+             ("ire_batch_options", ire.BatchOptions), ("ire_batch_stats", ire.BatchStats),
+             ("sur_train_opts", surrogate.TrainOpts)]
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "ire.h"', "int main(void) {"]
+    for cname, py in pairs:
+        lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {(a, b): int(c) for a, b, c in (l.split() for l in out if l)}
+    for cname, py in pairs:
+        assert got[(cname, "sizeof")] == ct.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

@@ -145,15 +145,20 @@ def test_parallel_weighted_against_oracle_ensemble(ire, opts):
     assert ok
 
 
-@pytest.mark.parametrize("name,factory,npk,gold", [
-    ("ext101_1e8", wl.cfg_external_large, dict(n_ext=100_000_000), "ext101_tau10_1e7"),
-    ("central200_1e8", wl.cfg_central, dict(n_ps=100_000_000), "central200_tau100_1e7"),
+@pytest.mark.parametrize("name,factory,npk,gold,opts", [
+    ("ext101_1e8", wl.cfg_external_large, dict(n_ext=100_000_000), "ext101_tau10_1e7", {}),
+    ("central200_1e8", wl.cfg_central, dict(n_ps=100_000_000), "central200_tau100_1e7", {}),
+    # eight accumulator groups of ~1.25e7 packages each: the mean of eight
+    # independent runs, against the oracle's mean of runs of 1e7 packages
+    ("ext101_1e8_replicas8", wl.cfg_external_large, dict(n_ext=100_000_000), "ext101_tau10_1e7", dict(replicas=8)),
+    ("central200_1e8_replicas8", wl.cfg_central, dict(n_ps=100_000_000), "central200_tau100_1e7",
+     dict(replicas=8)),
 ])
-def test_full_size_against_1e7_ensemble(ire, name, factory, npk, gold):
+def test_full_size_against_1e7_ensemble(ire, name, factory, npk, gold, opts):
     # full-size runs (as benchmarked) against the oracle's 16-seed ensemble at
     # 1e7 packages under the 1 % rule, plus exact energy bookkeeping
     g = golden(gold)
-    r = ire.run_model(factory(), seed=105, **npk)
+    r = ire.run_model(factory(), seed=105, **npk, **opts)
     assert_ensemble_parity(r["T"], g, name=name)
     s = r["stats"]
     out = sum(s["escaped"]) + s["ffi_escaped"] + s["terminated"]
@@ -238,7 +243,8 @@ def test_invalid_arguments_rejected(ire):
             h.run(0, 100, 1)           # no point source set
         assert e.value.code == ire.IRE_E_STATE
         for bad in (dict(k_bg=0.0), dict(k_A=0.0), dict(k_S=float("inf")), dict(use_g_E=1, g_E=1.0),
-                    dict(use_g_S=2), dict(ffi=3), dict(k_A_rho=1, k_A=2.0), dict(k_A_rho=1, k_A_lowest=0.0)):
+                    dict(use_g_S=2), dict(ffi=3), dict(k_A_rho=1, k_A=2.0), dict(k_A_rho=1, k_A_lowest=0.0),
+                    dict(replicas=0), dict(replicas=9), dict(replicas=2, max_lanes=1)):
             with pytest.raises(ire.IREError) as e:
                 h.set_options(**bad)
             assert e.value.code == ire.IRE_E_INVALID, bad
