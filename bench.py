@@ -29,7 +29,7 @@ if ROOT not in sys.path:
 # VALU instructions one lane executes per event on the FP32 tracer's paths
 # (least-squares fit of SQ_INSTS_VALU over one-lane runs of six clouds;
 # profiles/valu_fit_one_lane_clouds.md holds the fit and its command).
-VALU_PER_EVENT = {"cross": 23.87, "launch": 379.06, "scat": 295.52, "abs": 412.71}
+VALU_PER_EVENT = {"cross": 18.97, "launch": 277.35, "scat": 276.36, "abs": 331.36}
 
 # HBM bytes per tracer launch from FETCH_SIZE and WRITE_SIZE, scaled by a
 # plain 1 GiB copy (profiles/ire_trace_f32_ext101_tauV10_1e8.md); valid for
@@ -264,6 +264,10 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="ext101_tauV10_1e8", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--replicas", type=int, default=1,
+                    help="accumulator groups of the timed single-model launch (1: one running total per shell)")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the weighted and replica variants (profiling runs of the default launch)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
@@ -292,7 +296,9 @@ def main() -> int:
 
     h = ire.IREModel(0)
     h.set_model(model)
-    h.set_options(batch=int(os.environ.get("IRE_BENCH_BATCH", "0")), aggregate=int(os.environ.get("IRE_BENCH_AGG", "1")))
+    base_opts = dict(batch=int(os.environ.get("IRE_BENCH_BATCH", "0")),
+                     aggregate=int(os.environ.get("IRE_BENCH_AGG", "1")), replicas=args.replicas)
+    h.set_options(**base_opts)
 
     def step(seed: int):
         h.run(seed=seed, stream=stream, **{key: n_pkg})
@@ -317,17 +323,17 @@ def main() -> int:
     # background directions (Eq. 5, k_bg = 0.2) and the forced first interaction (Eqs. 9-12);
     # and eight independent accumulator groups instead of one running total per shell
     variants = {}
-    for vname, vopt in (("k_bg=0.2", dict(k_bg=0.2)), ("ffi", dict(ffi=1)), ("k_bg=0.2+ffi", dict(k_bg=0.2, ffi=1)),
-                        ("replicas=8", dict(replicas=8))):
-        h.set_options(batch=int(os.environ.get("IRE_BENCH_BATCH", "0")),
-                      aggregate=int(os.environ.get("IRE_BENCH_AGG", "1")), **vopt)
+    variant_opts = (("k_bg=0.2", dict(k_bg=0.2)), ("ffi", dict(ffi=1)), ("k_bg=0.2+ffi", dict(k_bg=0.2, ffi=1)),
+                    ("replicas=8", dict(replicas=8)))
+    for vname, vopt in () if args.no_variants else variant_opts:
+        h.set_options(**{**base_opts, **vopt})
         ms = []
         for s in range(2):
             step(20_000 + s)
             ms.append(h.stats()["ms_trace"])
         variants[vname] = {"kernel_ms": ms[-1], "kernel_packages_per_s": n_pkg / (ms[-1] * 1e-3),
                            "T_center_K": float(T[0].item())}
-    h.set_options(batch=int(os.environ.get("IRE_BENCH_BATCH", "0")), aggregate=int(os.environ.get("IRE_BENCH_AGG", "1")))
+    h.set_options(**base_opts)
 
     # PCIe-inclusive rate: host model in, host results out (reported, not the value)
     tp0 = time.perf_counter()
@@ -356,7 +362,8 @@ def main() -> int:
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": desc, "shells": n, "packages": n_pkg,
-                   "stepping": "fp32", "accumulators": "fp64", "parallelism": "single GPU"},
+                   "stepping": "fp32", "accumulators": "fp64", "accumulator_groups": args.replicas,
+                   "parallelism": "single GPU"},
         "kernel_ms_avg": k_ms,
         "kernel_packages_per_s": n_pkg / (k_ms * 1e-3),
         "events_per_launch": per_launch,
