@@ -146,7 +146,7 @@ def bench_surrogate(args) -> dict:
     env = os.environ.get
     n_train = int(env("IRE_SUR_TRAIN_MODELS", "200000"))
     train_scale = float(env("IRE_SUR_TRAIN_SCALE", "1.0"))
-    fit_steps = int(env("IRE_SUR_STEPS", "30000"))
+    fit_steps = int(env("IRE_SUR_STEPS", "60000"))
     n_eval = int(env("IRE_SUR_EVAL_MODELS", "1024"))
     ref_scale = float(env("IRE_SUR_REF_SCALE", "4.0"))
     n_inf = int(env("IRE_SUR_MODELS", "1000000"))

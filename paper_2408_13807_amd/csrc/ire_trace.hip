@@ -658,19 +658,44 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
                     t = 0;
                 }
                 if (o.ffi) {
-                    // extinction optical depth along the whole first ray
-                    R tau0 = 0, tt = t;
-                    for (const Shell *q = ps; q != sentinel;) {
-                        const Shell s = *q;
-                        const bool inward = (tt < (R)0) && (b2 < s.r2_in);
-                        const R arg = (inward ? s.r2_in : s.r2_out) - b2;
-                        const R sq = P<R>::sqrt_(arg > (R)0 ? arg : (R)0);
-                        const R tn = inward ? -sq : sq;
-                        const R lb = tn - tt > (R)0 ? tn - tt : (R)0;
-                        tau0 += d.kext * s.rho * lb;
-                        tt = tn;
-                        q += inward ? -1 : 1;
+                    // extinction optical depth along the whole first ray.  Its shells are
+                    // known in advance (inward from the surface down to the shell of the
+                    // tangent point and out again; outward from the centre), so each record
+                    // is requested one shell ahead of its use.  The outward half of an
+                    // inward ray mirrors its inward half.
+                    R col = 0;
+                    if (src == 0) {
+                        const Shell *q = sentinel - 1;
+                        Shell s = *q;
+                        const R a0 = s.r2_out - b2;
+                        R s_out = P<R>::sqrt_(a0 > (R)0 ? a0 : (R)0);
+                        for (;;) {
+                            const Shell nx = *(q > sh ? q - 1 : q);
+                            // the innermost record has r2_in = 0, so the loop ends there at the latest
+                            const bool tangent = !(b2 < s.r2_in);
+                            const R s_in = tangent ? (R)0 : P<R>::sqrt_(s.r2_in - b2);
+                            col += s.rho * (s_out - s_in);
+                            if (tangent) break;
+                            s_out = s_in;
+                            s = nx;
+                            --q;
+                        }
+                        col *= (R)2;
+                    } else {
+                        const Shell *q = sh;
+                        Shell s = *q;
+                        R r_in = 0;
+                        for (;;) {
+                            const Shell nx = *(q + 1 < sentinel ? q + 1 : q);
+                            const R r_out = P<R>::sqrt_(s.r2_out);
+                            col += s.rho * (r_out - r_in);
+                            if (q + 1 == sentinel) break;
+                            r_in = r_out;
+                            s = nx;
+                            ++q;
+                        }
                     }
+                    const R tau0 = d.kext * col;
                     if (!(tau0 > (R)0)) {
                         // no matter on the ray: the package leaves untouched
                         if (src == 0) lc.esc0 += eps * (double)W; else lc.esc1 += eps * (double)W;
