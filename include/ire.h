@@ -57,7 +57,8 @@ typedef struct ire_options {
     int32_t reemit_uniform; /* Sect. 4: re-emit at a uniformly random point of the shell volume (0/1) */
     int32_t aggregate;    /* 1: wave-level reduction of absorbed energy before the global atomic; 0: one atomic per lane */
     int32_t batch;        /* lanes of a wave parked at an event before their events are processed together
-                             (1..64; 0 = default 32); changes speed, not the distribution of results */
+                             (1..64, at most the wave's lanes with packages; 0 = default: 64 with replicas = 1,
+                             32 otherwise); changes speed, not the distribution of results */
     /* Sect. 2.2, Table 1: weighted sampling.  Reference direction: towards the
      * centre for packages of the external field, outwards for the point source. */
     int32_t use_g_E;      /* Eq. 6: re-emission cosine about the reference direction from HG(g_E), g_E in (-1,1) */

@@ -429,7 +429,10 @@ int ire_advance(ire_model *m, uint64_t n_ext, uint64_t n_ps, void *hip_stream) {
         unsigned long long c = (n_ext + n_ps) / (waves * 8ull);
         p.chunk = std::min<unsigned long long>(std::max<unsigned long long>(c, 64ull), 4096ull);
     }
-    p.batch = m->opt.batch > 0 ? m->opt.batch : 32;
+    // default event-pass threshold: with one running total per shell the returning atomics bound the
+    // launch, and waiting for every lane groups more absorptions per atomic; with accumulator groups the
+    // launch is instruction-bound and half the wave balances stepping against pass overhead
+    p.batch = m->opt.batch > 0 ? m->opt.batch : (m->replicas > 1 ? 32 : 64);
     if ((e = ire::launch_zero(nullptr, n, m->stats.p, 0, nullptr, 0, s)) != hipSuccess) return m->hip_fail(e, "cursor reset");
     if ((e = hipEventRecord(m->ev0, s)) != hipSuccess) return m->hip_fail(e, "event");
     if ((e = ire::launch_trace(p, fp64, m->opt.aggregate, grid, block, lds, s)) != hipSuccess)

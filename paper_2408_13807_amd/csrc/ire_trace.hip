@@ -769,8 +769,7 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
         // Four steps per check: a step of a parked package changes nothing.
         {
             const int live = __popcll(__ballot(st != ST_DONE));
-            const int half = (live + 1) / 2;
-            const int want = batch < half ? batch : (half > 0 ? half : 1);
+            const int want = batch < live ? batch : (live > 0 ? live : 1);
             fly = __ballot(st == ST_FLY);
             sweep_steps = 0;
             for (;;) {
