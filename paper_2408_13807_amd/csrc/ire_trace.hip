@@ -189,26 +189,33 @@ __device__ __forceinline__ double wave_excl_scan(double v) {
     return lane == 0 ? 0.0 : ex;
 }
 
-// Returning fetch-add of E into A[i] for the lanes with act set; every lane of
-// the wave must call it.  Each lane receives the value of A[i] just before its
-// own deposit.  With AGG, the lanes that hit the same shell are folded into one
-// deposit by their lowest lane (the group leader), and each member receives the
-// leader's base plus the energy of the lower lanes of its group.  The groups are
-// formed with ballots and shuffles first, so that the leaders of all groups
-// then issue their atomics as one instruction: one round trip to L2 per call,
-// however many shells the wave hits.
+// Returning fetch-add of E into A[i] for the lanes with act set, in two halves
+// so that independent work can run while the atomics are in flight: issue()
+// sends them, complete() waits and hands each lane the value of A[i] just
+// before its own deposit.  Every lane of the wave must call both.  With AGG,
+// the lanes that hit the same shell are folded into one deposit by their
+// lowest lane (the group leader), and each member receives the leader's base
+// plus the energy of the lower lanes of its group.  The groups are formed
+// with ballots and shuffles first, so that the leaders of all groups then
+// issue their atomics as one instruction: one round trip per call, however
+// many shells the wave hits.
+struct PendingAdd {
+    double raw = 0.0;     // the atomic's return value (group leaders, or every acting lane without AGG)
+    double ex = 0.0;      // energy of the lower lanes of this lane's group
+    int leader_of = 0;    // lane holding this lane's group base
+};
+
 template <bool AGG>
-__device__ __forceinline__ double fetch_add_energy(double *A, int i, double E, bool act) {
+__device__ __forceinline__ PendingAdd fetch_add_issue(double *A, int i, double E, bool act) {
+    PendingAdd q;
+    const int lane = __lane_id();
+    q.leader_of = lane;
     if constexpr (!AGG) {
-        double res = 0.0;
-        if (act) res = unsafeAtomicAdd(&A[(size_t)i * kAccStride], E);
-        return res;
+        if (act) q.raw = unsafeAtomicAdd(&A[(size_t)i * kAccStride], E);
+        return q;
     } else {
-        const int lane = __lane_id();
         unsigned long long pending = __ballot(act);
         double dep = 0.0;     // the leader's deposit: its group's total energy
-        double ex = 0.0;      // energy of the lower lanes of this lane's group
-        int leader_of = lane;
         bool lead = false;
         while (pending) {
             const int leader = __ffsll((long long)pending) - 1;
@@ -226,8 +233,8 @@ __device__ __forceinline__ double fetch_add_energy(double *A, int i, double E, b
                 const double e = wave_excl_scan(v);
                 const double tot = __shfl(e + v, kWave - 1, kWave);
                 if (mine) {
-                    ex = e;
-                    leader_of = leader;
+                    q.ex = e;
+                    q.leader_of = leader;
                 }
                 if (lane == leader) {
                     dep = tot;
@@ -235,10 +242,18 @@ __device__ __forceinline__ double fetch_add_energy(double *A, int i, double E, b
                 }
             }
         }
-        double base = 0.0;
-        if (lead) base = unsafeAtomicAdd(&A[(size_t)i * kAccStride], dep);
-        base = __shfl(base, leader_of, kWave);
-        return act ? base + ex : 0.0;
+        if (lead) q.raw = unsafeAtomicAdd(&A[(size_t)i * kAccStride], dep);
+        return q;
+    }
+}
+
+template <bool AGG>
+__device__ __forceinline__ double fetch_add_complete(const PendingAdd &q, bool act) {
+    if constexpr (!AGG) {
+        return act ? q.raw : 0.0;
+    } else {
+        const double base = __shfl(q.raw, q.leader_of, kWave);
+        return act ? base + q.ex : 0.0;
     }
 }
 
@@ -540,11 +555,15 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
             // slice [A_before, A_before + E] of the shell's absorbed power
             const double E = absorbing ? eps * (double)W : 0.0;
             const double invM = absorbing ? mc.a_scale * mc.invM[i - cav] : 0.0;   // issued before the atomic's round trip
-            double A_before = 0.0;
-            if (__ballot(absorbing)) A_before = fetch_add_energy<AGG>(mc.A, i - cav, E, absorbing);
+            // the atomics go out first; the shared Philox block is computed while they are in flight
+            const bool any_abs = __ballot(absorbing) != 0;
+            PendingAdd pend;
+            if (any_abs) pend = fetch_add_issue<AGG>(mc.A, i - cav, E, absorbing);
 
             Rand4 r1{0, 0, 0, 0}, r2b{0, 0, 0, 0};
             if (ev) r1 = philox(blk++, pid_lo, pid_hi, (uint32_t)src, key0, key1);
+            double A_before = 0.0;
+            if (any_abs) A_before = fetch_add_complete<AGG>(pend, absorbing);
 
             // re-emission: a* uniform in the package's slice [A_before, A_before + E] / M
             // selects the G(T) bin whose difference spectrum is drawn.  A slice almost
