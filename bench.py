@@ -87,6 +87,11 @@ def bench_batch(args) -> dict:
     params = workloads.batch_parameters(4096, seed=3)
     torch.cuda.set_device(0)
     b = ire.batch_from_workloads(params, package_scale=scale)
+    # schedule knobs for experiments (defaults otherwise)
+    knobs = {k: int(os.environ[e]) for k, e in (("aggregate", "IRE_BENCH_AGG"), ("batch", "IRE_BENCH_BATCH"))
+             if e in os.environ}
+    if knobs:
+        b.set_options(**knobs)
     n_pkg = int(sum(max(1, round(int(x) * scale)) for x in params["n_pkg"]))
     for w in range(args.warmup):
         b.run()
@@ -97,7 +102,7 @@ def bench_batch(args) -> dict:
         b.run()
         st = b.results(allow_limit=True)["stats"]
         ms.append(st["ms_run"])
-        ev = st if ev is None else {k: ev[k] + st[k] for k in ("n_cross", "n_launch", "n_scat", "n_abs", "n_pass")}
+        ev = st if ev is None else {k: ev[k] + st[k] for k in ("n_cross", "n_launch", "n_scat", "n_abs", "n_pass", "n_step_slots")}
     t1 = time.perf_counter()
     b.close()
     # per-model launches of a sample of the same models (same budgets)
@@ -113,7 +118,7 @@ def bench_batch(args) -> dict:
         t_single += time.perf_counter() - ts
     single_models_per_s = len(sample) / t_single
     k_ms = sum(ms) / len(ms)
-    per_launch = {k: ev[k] / args.steps for k in ("n_cross", "n_launch", "n_scat", "n_abs", "n_pass")}
+    per_launch = {k: ev[k] / args.steps for k in ("n_cross", "n_launch", "n_scat", "n_abs", "n_pass", "n_step_slots")}
     achieved = algorithmic_ops(per_launch) / (k_ms * 1e-3) / 1e12
     value = 4096 * args.steps / (t1 - t0)
     return {
@@ -315,7 +320,7 @@ def main() -> int:
         step(1 + s)
         st = h.stats()           # synchronises; tracing-kernel time from HIP events on `stream`
         kernel_ms.append(st["ms_trace"])
-        events = st if events is None else {k: events[k] + st[k] for k in ("n_cross", "n_launch", "n_scat", "n_abs", "n_pass")}
+        events = st if events is None else {k: events[k] + st[k] for k in ("n_cross", "n_launch", "n_scat", "n_abs", "n_pass", "n_step_slots")}
     torch.cuda.synchronize()
     t1 = time.perf_counter()
 
@@ -345,7 +350,7 @@ def main() -> int:
     ms_step = (t1 - t0) * 1e3 / args.steps
     value = n_pkg * args.steps / (t1 - t0)
     k_ms = sum(kernel_ms) / len(kernel_ms)
-    per_launch = {k: events[k] / args.steps for k in ("n_cross", "n_launch", "n_scat", "n_abs", "n_pass")}
+    per_launch = {k: events[k] / args.steps for k in ("n_cross", "n_launch", "n_scat", "n_abs", "n_pass", "n_step_slots")}
     ops = algorithmic_ops(per_launch)
     achieved = ops / (k_ms * 1e-3) / 1e12
     line = {

@@ -93,6 +93,8 @@ typedef struct ire_stats {
     uint64_t n_reemit_above;   /* re-emission draws above the last temperature table point */
     uint64_t n_pass;           /* event passes of the tracer's waves (each handles the interactions,
                                   escapes and launches of the wave's parked lanes together) */
+    uint64_t n_step_slots;     /* lane slots of the crossing sweeps (64 per wave-level step); n_cross /
+                                  n_step_slots is the share of them that moved a package */
     float ms_tables, ms_trace, ms_finalize; /* host table build, tracing kernel, finalize kernel */
 } ire_stats;
 
@@ -223,6 +225,7 @@ typedef struct ire_batch_stats {
     uint64_t n_launch, n_cross, n_scat, n_abs, n_escape, n_limit, n_floor, n_below, n_above;
     uint64_t n_models, n_items, n_shells;
     uint64_t n_pass;           /* event passes of the tracer's waves */
+    uint64_t n_step_slots;     /* lane slots of the crossing sweeps (64 per wave-level step) */
     float ms_run;              /* zero + trace + finalize on the device (HIP events) */
 } ire_batch_stats;
 

@@ -499,6 +499,7 @@ static void fill_stats(const ire_model *m, const ire::DevStats &hs, ire_stats *s
         stats->n_above = hs.cnt[ire::C_ABOVE];
         stats->n_reemit_above = hs.cnt[ire::C_REEMIT_ABOVE];
         stats->n_pass = hs.cnt[ire::C_PASS];
+        stats->n_step_slots = hs.cnt[ire::C_SLOTS];
         stats->ms_tables = m->ms_tables;
         stats->ms_trace = m->ms_trace;
         stats->ms_finalize = m->ms_finalize;

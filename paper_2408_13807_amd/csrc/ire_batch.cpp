@@ -517,6 +517,7 @@ int ire_batch_get(ire_batch *b, double *A_flat, double *T_flat, ire_batch_stats 
         st->n_below = hs.cnt[ire::C_BELOW];
         st->n_above = hs.cnt[ire::C_ABOVE];
         st->n_pass = hs.cnt[ire::C_PASS];
+        st->n_step_slots = hs.cnt[ire::C_SLOTS];
         st->n_models = b->models.size();
         st->n_items = b->items.size();
         st->n_shells = b->n_shells;

@@ -43,7 +43,7 @@ struct DustD { double kA, kS, inv_kA, inv_kS, g, alb, kext, pad; };
 
 enum Counter {
     C_LAUNCH, C_CROSS, C_SCAT, C_ABS, C_ESCAPE, C_DIRECT, C_LIMIT, C_FLOOR,
-    C_REEMIT_ABOVE, C_BELOW, C_ABOVE, C_PASS, C_COUNT
+    C_REEMIT_ABOVE, C_BELOW, C_ABOVE, C_PASS, C_SLOTS, C_COUNT
 };
 enum Tally { T_ESC_EXT, T_ESC_PS, T_FFI, T_TERM, T_COUNT };
 

@@ -280,6 +280,7 @@ struct LaneCounters {
     // lane); the crossings are these less the steps into the sentinel (`sent`)
     unsigned long long steps = 0;
     uint32_t passes = 0;           // event passes of this wave (the same value in every lane)
+    unsigned long long slots = 0;  // lane slots of its crossing sweeps: 64 per wave-level step
     double esc0 = 0.0, esc1 = 0.0, ffi = 0.0, term = 0.0;
 };
 
@@ -798,6 +799,7 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
                 step();
                 step();
                 step();
+                lc.slots += 4 * kWave;
             }
             st = (st == ST_FLY && !__builtin_amdgcn_inverse_ballot_w64(fly)) ? (int)ST_EVT : st;
             lc.steps += sweep_steps;
@@ -818,13 +820,14 @@ __device__ __forceinline__ void flush_counters(const LaneCounters &lc, DevStats 
     const int lane = __lane_id();
     // modular: the wave's sum is the number of crossings
     const unsigned long long cross = (lane == 0 ? lc.steps : 0ull) - (unsigned long long)lc.sent;
-    const unsigned long long cs[10] = {lc.launch, cross, lc.scat, lc.abs, lc.escape,
+    const unsigned long long cs[11] = {lc.launch, cross, lc.scat, lc.abs, lc.escape,
                                        lc.direct, lc.limit, lc.floor, lc.reabove,
-                                       lane == 0 ? (unsigned long long)lc.passes : 0ull};
-    const int cidx[10] = {C_LAUNCH, C_CROSS, C_SCAT, C_ABS, C_ESCAPE, C_DIRECT, C_LIMIT, C_FLOOR, C_REEMIT_ABOVE,
-                          C_PASS};
+                                       lane == 0 ? (unsigned long long)lc.passes : 0ull,
+                                       lane == 0 ? lc.slots : 0ull};
+    const int cidx[11] = {C_LAUNCH, C_CROSS, C_SCAT, C_ABS, C_ESCAPE, C_DIRECT, C_LIMIT, C_FLOOR, C_REEMIT_ABOVE,
+                          C_PASS, C_SLOTS};
 #pragma unroll
-    for (int j = 0; j < 10; ++j) {
+    for (int j = 0; j < 11; ++j) {
         const unsigned long long v = wave_sum_u64(cs[j]);
         if (lane == 0 && v) atomicAdd(&stats->cnt[cidx[j]], v);
     }

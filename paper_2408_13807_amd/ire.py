@@ -48,7 +48,7 @@ class Stats(ct.Structure):
     _fields_ = [("L_ext", ct.c_double), ("L_ps", ct.c_double), ("escaped", ct.c_double * 2),
                 ("ffi_escaped", ct.c_double), ("terminated", ct.c_double)] + [
         (f, ct.c_uint64) for f in ("n_launch", "n_cross", "n_scat", "n_abs", "n_escape", "n_direct",
-                                   "n_limit", "n_floor", "n_below", "n_above", "n_reemit_above", "n_pass")] + [
+                                   "n_limit", "n_floor", "n_below", "n_above", "n_reemit_above", "n_pass", "n_step_slots")] + [
         ("ms_tables", ct.c_float), ("ms_trace", ct.c_float), ("ms_finalize", ct.c_float)]
 
 
@@ -75,7 +75,7 @@ class BatchStats(ct.Structure):
     _fields_ = [("L_total", ct.c_double), ("escaped", ct.c_double), ("ffi_escaped", ct.c_double),
                 ("terminated", ct.c_double)] + [
         (f, ct.c_uint64) for f in ("n_launch", "n_cross", "n_scat", "n_abs", "n_escape", "n_limit", "n_floor",
-                                   "n_below", "n_above", "n_models", "n_items", "n_shells", "n_pass")] + [
+                                   "n_below", "n_above", "n_models", "n_items", "n_shells", "n_pass", "n_step_slots")] + [
         ("ms_run", ct.c_float)]
 
 
