@@ -19,6 +19,13 @@ constexpr int kSentinels = 2;
 constexpr int kPadBelow = 1;
 // Largest number of independent accumulator groups of a single-model run.
 constexpr int kMaxReplicas = 8;
+// Slots of a wave's LDS scratch for grouping its absorptions by shell (a power
+// of two), and the scratch of a workgroup of `block` threads (plus 8 bytes for
+// aligning it after tables of 4-byte entries).
+constexpr int kAggSlots = 32;
+__host__ __device__ inline size_t agg_lds_bytes(int block) {
+    return (size_t)(block / 64) * kAggSlots * (sizeof(double) + sizeof(int)) + 8;
+}
 // Guide tables (cut-point method, Chen & Asau 1974) accelerate the searches
 // of the G(T) table and of the frequency CDFs; the searches stay exact (a
 // bidirectional scan from the guide's start).  Layout of the guide bytes:

@@ -177,6 +177,21 @@ __device__ __forceinline__ R hg_pdf(R g, R mu) {
 // ---------------------------------------------------------------------------
 // Wave-level helpers (wave64)
 
+// Orders the LDS accesses of the wave's lanes before it against those after it
+// (the hardware runs a wave's LDS operations in order; this keeps the compiler
+// from moving them across).
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One wave's LDS scratch for grouping its absorptions by shell.
+struct AggScratch {
+    double sum[kAggSlots];
+    int owner[kAggSlots];
+};
+
 __device__ __forceinline__ double wave_excl_scan(double v) {
     const int lane = __lane_id();
     double incl = v;
@@ -193,20 +208,24 @@ __device__ __forceinline__ double wave_excl_scan(double v) {
 // so that independent work can run while the atomics are in flight: issue()
 // sends them, complete() waits and hands each lane the value of A[i] just
 // before its own deposit.  Every lane of the wave must call both.  With AGG,
-// the lanes that hit the same shell are folded into one deposit by their
-// lowest lane (the group leader), and each member receives the leader's base
-// plus the energy of the lower lanes of its group.  The groups are formed
-// with ballots and shuffles first, so that the leaders of all groups then
+// the lanes that hit the same shell are folded into one deposit by a group
+// leader, and each member receives the leader's base plus its own offset
+// inside the group's deposit, so that the members' slices tile the deposit.
+// Groups form in the wave's LDS scratch first: every lane writes its lane id
+// into the slot (shell mod kAggSlots) and reads back the winner; the lanes of
+// the winner's shell add their energies to the slot's sum with returning LDS
+// atomics (the returned value is the offset).  The few lanes whose slot went
+// to another shell are grouped with ballots and shuffles.  All leaders then
 // issue their atomics as one instruction: one round trip per call, however
 // many shells the wave hits.
 struct PendingAdd {
     double raw = 0.0;     // the atomic's return value (group leaders, or every acting lane without AGG)
-    double ex = 0.0;      // energy of the lower lanes of this lane's group
+    double ex = 0.0;      // this lane's offset inside its group's deposit
     int leader_of = 0;    // lane holding this lane's group base
 };
 
 template <bool AGG>
-__device__ __forceinline__ PendingAdd fetch_add_issue(double *A, int i, double E, bool act) {
+__device__ __forceinline__ PendingAdd fetch_add_issue(double *A, int i, double E, bool act, AggScratch *ws) {
     PendingAdd q;
     const int lane = __lane_id();
     q.leader_of = lane;
@@ -214,13 +233,30 @@ __device__ __forceinline__ PendingAdd fetch_add_issue(double *A, int i, double E
         if (act) q.raw = unsafeAtomicAdd(&A[(size_t)i * kAccStride], E);
         return q;
     } else {
-        unsigned long long pending = __ballot(act);
+        // groups by slot; the wave's LDS operations complete in program order
+        const int slot = i & (kAggSlots - 1);
+        if (act) ws->owner[slot] = lane;
+        wave_sync_lds();
+        const int owner = act ? ws->owner[slot] : lane;
+        const bool member = act && __shfl(i, owner, kWave) == i;
+        if (member && owner == lane) ws->sum[slot] = 0.0;
+        wave_sync_lds();
+        if (member) q.ex = atomicAdd(&ws->sum[slot], E);
+        wave_sync_lds();
         double dep = 0.0;     // the leader's deposit: its group's total energy
         bool lead = false;
+        if (member && owner == lane) {
+            dep = ws->sum[slot];
+            lead = true;
+        }
+        if (member) q.leader_of = owner;
+        // the rest: groups by ballots over the lanes whose slot holds another shell
+        const bool rest = act && !member;
+        unsigned long long pending = __ballot(rest);
         while (pending) {
             const int leader = __ffsll((long long)pending) - 1;
             const int s = __shfl(i, leader, kWave);
-            const unsigned long long grp = __ballot(act && i == s);
+            const unsigned long long grp = __ballot(rest && i == s);
             pending &= ~grp;
             const bool mine = (grp >> lane) & 1ull;
             if (__popcll(grp) == 1) {
@@ -320,7 +356,7 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
                                             const unsigned char *guide, float g_lg0, float g_scale,
                                             const typename P<R>::KRec *rk,
                                             unsigned long long *cursor, unsigned long long chunk,
-                                            bool lane_off, LaneCounters &lc, double *sed) {
+                                            bool lane_off, LaneCounters &lc, double *sed, AggScratch *agg) {
     using Shell = typename P<R>::Shell;
     using Dust = typename P<R>::Dust;
     using KRec = typename P<R>::KRec;
@@ -559,7 +595,7 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
             // the atomics go out first; the shared Philox block is computed while they are in flight
             const bool any_abs = __ballot(absorbing) != 0;
             PendingAdd pend;
-            if (any_abs) pend = fetch_add_issue<AGG>(mc.A, i - cav, E, absorbing);
+            if (any_abs) pend = fetch_add_issue<AGG>(mc.A, i - cav, E, absorbing, agg);
 
             Rand4 r1{0, 0, 0, 0}, r2b{0, 0, 0, 0};
             if (ev) r1 = philox(blk++, pid_lo, pid_hi, (uint32_t)src, key0, key1);
@@ -902,6 +938,7 @@ __global__ __launch_bounds__(kBlockFP32) void ire_trace_f32(TraceParams p) {
     float2 *s_rk = reinterpret_cast<float2 *>(s_sed + 4 * K) + kPadBelow;
     if constexpr (WT == 2)
         for (int j = threadIdx.x - kPadBelow; j < nsh; j += blockDim.x) s_rk[j] = j < 0 ? float2{0, 0} : p.rkf[j];
+    AggScratch *s_agg = reinterpret_cast<AggScratch *>(s_rk + nsh);
     __syncthreads();
     ModelCtx<float> mc;
     MethodOpts o;
@@ -910,7 +947,7 @@ __global__ __launch_bounds__(kBlockFP32) void ire_trace_f32(TraceParams p) {
     LaneCounters lc;
     trace_model<float, AGG, WT>(mc, o, s_dust, s_cdf, s_G, s_D, K, n_t, reinterpret_cast<const unsigned char *>(s_guide),
                                 p.g_lg0, p.g_scale, s_rk, &p.stats->cursor, p.chunk,
-                                 p.max_lanes > 0 && gtid >= p.max_lanes, lc, s_sed);
+                                 p.max_lanes > 0 && gtid >= p.max_lanes, lc, s_sed, s_agg + threadIdx.x / kWave);
     flush_counters(lc, p.stats);
     flush_sed(s_sed, 4 * K, p.sed);
 }
@@ -927,7 +964,8 @@ __global__ __launch_bounds__(256) void ire_trace_f64(TraceParams p) {
     const long long gtid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     LaneCounters lc;
     trace_model<double, AGG, WT>(mc, o, p.dustd, p.cdfd, p.Gd, p.Dd, p.K, p.n_t, p.guide, p.g_lg0, p.g_scale,
-                                 p.rkd, &p.stats->cursor, p.chunk, p.max_lanes > 0 && gtid >= p.max_lanes, lc, s_sed);
+                                 p.rkd, &p.stats->cursor, p.chunk, p.max_lanes > 0 && gtid >= p.max_lanes, lc, s_sed,
+                                 reinterpret_cast<AggScratch *>(s_sed + 4 * p.K) + threadIdx.x / kWave);
     flush_counters(lc, p.stats);
     flush_sed(s_sed, 4 * p.K, p.sed);
 }
@@ -1001,6 +1039,7 @@ __global__ __launch_bounds__(kBlockFP32) void ire_trace_batch(BatchParams p) {
     for (int j = threadIdx.x; j < nd; j += blockDim.x) s_D[j] = p.Df[j];
     const int ng = (int)(guide_bytes(n_t) / 4);
     for (int j = threadIdx.x; j < ng; j += blockDim.x) s_guide[j] = reinterpret_cast<const uint32_t *>(p.guide)[j];
+    AggScratch *s_agg = reinterpret_cast<AggScratch *>((reinterpret_cast<uintptr_t>(s_guide + ng) + 7) & ~(uintptr_t)7);
 
     MethodOpts o;
     o.k_bg = p.k_bg;
@@ -1047,7 +1086,7 @@ __global__ __launch_bounds__(kBlockFP32) void ire_trace_batch(BatchParams p) {
         trace_model<float, AGG, WT>(mc, o, s_dust, s_cdf, s_G, s_D, K, n_t,
                                     reinterpret_cast<const unsigned char *>(s_guide), p.g_lg0, p.g_scale, nullptr,
                                     &s_cursor,
-                                     64ull, false, lc, nullptr);
+                                     64ull, false, lc, nullptr, s_agg + threadIdx.x / kWave);
     }
     flush_counters(lc, p.stats);
 }
@@ -1090,7 +1129,8 @@ __global__ void ire_finalize_batch(BatchFinalizeParams p) {
 size_t trace_lds_bytes(int n_table, int K, int n_t) {
     return (size_t)(n_table + kPadBelow) * sizeof(ShellF) + (size_t)K * sizeof(DustF) +
            (size_t)2 * K * sizeof(float) + (size_t)n_t * sizeof(float) + (size_t)n_t * K * sizeof(float) +
-           guide_bytes(n_t) + sed_lds_bytes(K) + (size_t)(n_table + kPadBelow) * sizeof(float2);
+           guide_bytes(n_t) + sed_lds_bytes(K) + (size_t)(n_table + kPadBelow) * sizeof(float2) +
+           agg_lds_bytes(kBlockFP32);
 }
 
 size_t sed_lds_bytes(int K) { return (size_t)4 * K * sizeof(double); }
@@ -1146,7 +1186,7 @@ hipError_t launch_trace(const TraceParams &p, int fp64, int aggregate, int grid,
     TraceParams q = p;
     void *args[] = {&q};
     if (fp64) return hipLaunchKernel(f64_kernel(aggregate, weighting(p)), dim3(grid), dim3(block), args,
-                                     sed_lds_bytes(p.K), s);
+                                     sed_lds_bytes(p.K) + agg_lds_bytes(block), s);
     return hipLaunchKernel(f32_kernel(aggregate, weighting(p)), dim3(grid), dim3(block), args, lds, s);
 }
 
