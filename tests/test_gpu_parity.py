@@ -166,11 +166,19 @@ def test_full_size_against_1e7_ensemble(ire, name, factory, npk, gold, opts):
     assert s["n_launch"] == sum(npk.values()) and s["n_escape"] == sum(npk.values())
 
 
-@pytest.mark.parametrize("opts", [dict(batch=1), dict(batch=64), dict(aggregate=0)])
+@pytest.mark.parametrize("opts", [dict(batch=1), dict(batch=32), dict(batch=64), dict(aggregate=0),
+                                  dict(replicas=2, batch=48)])
 def test_schedule_options_do_not_change_results(ire, opts):
     g = golden("ext50_tau1_1e5")
     r = ire.run_model(wl.cfg_external_small(), n_ext=100_000, seed=106, **opts)
     assert_ensemble_parity(r["T"], g, name=f"ext50 {opts}")
+    # schedule statistics: a pass handles at most a wave's 64 lanes, sweeps run
+    # in groups of four wave-level steps, and a crossing takes one lane slot
+    s = r["stats"]
+    events = s["n_launch"] + s["n_scat"] + s["n_abs"]
+    assert s["n_pass"] * 64 >= events
+    assert s["n_step_slots"] % (4 * 64) == 0
+    assert 0 < s["n_cross"] <= s["n_step_slots"]
 
 
 def test_parallel_sed_against_oracle_ensemble(ire):
