@@ -55,7 +55,9 @@ typedef struct ire_options {
     int32_t stepping;     /* IRE_FP32 or IRE_FP64 */
     int32_t max_lanes;    /* 0: fill the device; n > 0: at most n packages in flight (1 = serial order) */
     int32_t reemit_uniform; /* Sect. 4: re-emit at a uniformly random point of the shell volume (0/1) */
-    int32_t aggregate;    /* 1: wave-level reduction of absorbed energy before the global atomic; 0: one atomic per lane */
+    int32_t aggregate;    /* how the absorptions of a pass are folded before the returning global atomics:
+                             0: one atomic per lane; 1: per wave, by shell; 2: per workgroup, by shell (the
+                             workgroup's waves then run their event passes together; fewer than 2^22 shells) */
     int32_t batch;        /* lanes of a wave parked at an event before their events are processed together
                              (1..64, at most the wave's lanes with packages; 0 = default: 64 with replicas = 1,
                              32 otherwise); changes speed, not the distribution of results */
@@ -208,7 +210,7 @@ typedef struct ire_batch_options {
     double w_floor;
     uint64_t max_events;
     int32_t reemit_uniform;
-    int32_t aggregate;
+    int32_t aggregate;        /* 0 or 1 as in ire_options (the workgroup grouping is single-model only) */
     int32_t batch;            /* lanes parked at an event before the wave processes events (0 = 32) */
     uint64_t item_packages;   /* packages per work item; a model is split into items (0 = 524288) */
     int32_t use_graph;        /* 1: replay zero/trace/finalize as a captured HIP graph (default) */

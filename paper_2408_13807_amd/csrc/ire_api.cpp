@@ -328,7 +328,7 @@ int ire_set_options(ire_model *m, const ire_options *o) {
         return m->fail(IRE_E_INVALID, "k_A_rho needs k_A = 1 and finite k_A_lowest, k_A_highest > 0");
     if (o->k_A_lowest != m->opt.k_A_lowest || o->k_A_highest != m->opt.k_A_highest) m->dirty = true;
     if (o->reemit_uniform != 0 && o->reemit_uniform != 1) return m->fail(IRE_E_INVALID, "reemit_uniform must be 0 or 1");
-    if (o->aggregate != 0 && o->aggregate != 1) return m->fail(IRE_E_INVALID, "aggregate must be 0 or 1");
+    if (o->aggregate < 0 || o->aggregate > 2) return m->fail(IRE_E_INVALID, "aggregate must be 0, 1 or 2");
     if (o->batch < 0 || o->batch > 64) return m->fail(IRE_E_INVALID, "batch must be in [0, 64]");
     if (o->replicas < 1 || o->replicas > ire::kMaxReplicas)
         return m->fail(IRE_E_INVALID, "replicas must be in [1, %d]", ire::kMaxReplicas);
@@ -378,6 +378,8 @@ int ire_advance(ire_model *m, uint64_t n_ext, uint64_t n_ps, void *hip_stream) {
     if (n_ext + n_ps == 0) return IRE_OK;
     if (m->replicas > 1 && m->opt.max_lanes > 0)
         return m->fail(IRE_E_STATE, "a run begun with replicas > 1 cannot continue with max_lanes > 0");
+    if (m->opt.aggregate == 2 && m->rho.size() >= (1u << 22))
+        return m->fail(IRE_E_INVALID, "aggregate = 2 supports fewer than 2^22 shells");
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
     hipError_t e;
     if ((e = hipSetDevice(m->device)) != hipSuccess) return m->hip_fail(e, "hipSetDevice");

@@ -23,8 +23,13 @@ constexpr int kMaxReplicas = 8;
 // of two), and the scratch of a workgroup of `block` threads (plus 8 bytes for
 // aligning it after tables of 4-byte entries).
 constexpr int kAggSlots = 32;
+// Slots of a workgroup's LDS scratch for grouping the absorptions of all its
+// waves by shell (aggregate = 2): key, group sum and group base per slot.
+constexpr int kWgSlots = 256;
 __host__ __device__ inline size_t agg_lds_bytes(int block) {
-    return (size_t)(block / 64) * kAggSlots * (sizeof(double) + sizeof(int)) + 8;
+    const size_t wave = (size_t)(block / 64) * kAggSlots * (sizeof(double) + sizeof(int));
+    const size_t wg = (size_t)kWgSlots * (2 * sizeof(double) + sizeof(unsigned));
+    return (wave > wg ? wave : wg) + 8;
 }
 // Guide tables (cut-point method, Chen & Asau 1974) accelerate the searches
 // of the G(T) table and of the frequency CDFs; the searches stay exact (a

@@ -192,6 +192,13 @@ struct AggScratch {
     int owner[kAggSlots];
 };
 
+// A workgroup's LDS scratch for grouping the absorptions of all its waves.
+struct WgScratch {
+    double sum[kWgSlots];
+    double base[kWgSlots];
+    unsigned key[kWgSlots];
+};
+
 __device__ __forceinline__ double wave_excl_scan(double v) {
     const int lane = __lane_id();
     double incl = v;
@@ -224,12 +231,12 @@ struct PendingAdd {
     int leader_of = 0;    // lane holding this lane's group base
 };
 
-template <bool AGG>
+template <int AGG>
 __device__ __forceinline__ PendingAdd fetch_add_issue(double *A, int i, double E, bool act, AggScratch *ws) {
     PendingAdd q;
     const int lane = __lane_id();
     q.leader_of = lane;
-    if constexpr (!AGG) {
+    if constexpr (AGG == 0) {
         if (act) q.raw = unsafeAtomicAdd(&A[(size_t)i * kAccStride], E);
         return q;
     } else {
@@ -283,14 +290,84 @@ __device__ __forceinline__ PendingAdd fetch_add_issue(double *A, int i, double E
     }
 }
 
-template <bool AGG>
+template <int AGG>
 __device__ __forceinline__ double fetch_add_complete(const PendingAdd &q, bool act) {
-    if constexpr (!AGG) {
+    if constexpr (AGG == 0) {
         return act ? q.raw : 0.0;
     } else {
         const double base = __shfl(q.raw, q.leader_of, kWave);
         return act ? base + q.ex : 0.0;
     }
+}
+
+// The same for all waves of a workgroup together (aggregate = 2): the lanes of
+// every wave that hit a shell are folded into one deposit, so one atomic per
+// shell and pass leaves the workgroup.  Slots are keyed by shell and thread
+// (shell mod kWgSlots); the lanes whose slot went to another shell fall back
+// to their wave's ballot grouping.  Every thread of the workgroup must call
+// both halves in every pass (they hold workgroup barriers).
+struct PendingWg {
+    PendingAdd w;          // the wave-level result for the lanes outside the slot groups
+    double off = 0.0;      // offset inside the slot group's deposit
+    int slot = 0;
+    bool member = false, owner = false;
+};
+
+__device__ __forceinline__ PendingWg fetch_add_issue_wg(double *A, int i, double E, bool act, WgScratch *wg) {
+    PendingWg g;
+    const int tid = (int)threadIdx.x;
+    g.slot = i & (kWgSlots - 1);
+    const unsigned key = ((unsigned)i << 10) | (unsigned)tid;   // i < 2^22, tid < 1024
+    if (act) wg->key[g.slot] = key;
+    __syncthreads();
+    const unsigned kr = act ? wg->key[g.slot] : 0u;
+    g.member = act && (int)(kr >> 10) == i;
+    g.owner = g.member && (int)(kr & 1023u) == tid;
+    if (g.owner) wg->sum[g.slot] = 0.0;
+    __syncthreads();
+    if (g.member) g.off = atomicAdd(&wg->sum[g.slot], E);
+    __syncthreads();
+    // slot owners deposit their group's total; the rest group within their wave
+    const bool rest = act && !g.member;
+    PendingAdd w;
+    const int lane = __lane_id();
+    w.leader_of = lane;
+    double dep = 0.0;
+    bool lead = false;
+    if (g.owner) {
+        dep = wg->sum[g.slot];
+        lead = true;
+    }
+    unsigned long long pending = __ballot(rest);
+    while (pending) {
+        const int leader = __ffsll((long long)pending) - 1;
+        const int s = __shfl(i, leader, kWave);
+        const unsigned long long grp = __ballot(rest && i == s);
+        pending &= ~grp;
+        const bool mine = (grp >> lane) & 1ull;
+        const double v = mine ? E : 0.0;
+        const double e = wave_excl_scan(v);
+        const double tot = __shfl(e + v, kWave - 1, kWave);
+        if (mine) {
+            w.ex = e;
+            w.leader_of = leader;
+        }
+        if (lane == leader) {
+            dep = tot;
+            lead = true;
+        }
+    }
+    if (lead) w.raw = unsafeAtomicAdd(&A[(size_t)i * kAccStride], dep);
+    g.w = w;
+    return g;
+}
+
+__device__ __forceinline__ double fetch_add_complete_wg(const PendingWg &g, bool act, WgScratch *wg) {
+    if (g.owner) wg->base[g.slot] = g.w.raw;
+    const double wbase = __shfl(g.w.raw, g.w.leader_of, kWave);
+    __syncthreads();
+    if (!act) return 0.0;
+    return g.member ? wg->base[g.slot] + g.off : wbase + g.w.ex;
 }
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
@@ -349,14 +426,15 @@ struct MethodOpts {
 // Trace every package of one model with the lanes of this wave.  Package
 // indices come from `cursor` (global or LDS memory) `chunk` at a time; the
 // call returns when the cursor is exhausted and every lane is idle.
-template <typename R, bool AGG, int WT>
+template <typename R, int AGG, int WT>
 __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodOpts &o,
                                             const typename P<R>::Dust *dust, const R *cdf,
                                             const R *G, const R *D, int K, int n_t,
                                             const unsigned char *guide, float g_lg0, float g_scale,
                                             const typename P<R>::KRec *rk,
                                             unsigned long long *cursor, unsigned long long chunk,
-                                            bool lane_off, LaneCounters &lc, double *sed, AggScratch *agg) {
+                                            bool lane_off, LaneCounters &lc, double *sed, AggScratch *agg,
+                                            WgScratch *wg) {
     using Shell = typename P<R>::Shell;
     using Dust = typename P<R>::Dust;
     using KRec = typename P<R>::KRec;
@@ -595,12 +673,15 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
             // the atomics go out first; the shared Philox block is computed while they are in flight
             const bool any_abs = __ballot(absorbing) != 0;
             PendingAdd pend;
-            if (any_abs) pend = fetch_add_issue<AGG>(mc.A, i - cav, E, absorbing, agg);
+            PendingWg pwg;
+            if constexpr (AGG == 2) pwg = fetch_add_issue_wg(mc.A, i - cav, E, absorbing, wg);
+            else if (any_abs) pend = fetch_add_issue<AGG>(mc.A, i - cav, E, absorbing, agg);
 
             Rand4 r1{0, 0, 0, 0}, r2b{0, 0, 0, 0};
             if (ev) r1 = philox(blk++, pid_lo, pid_hi, (uint32_t)src, key0, key1);
             double A_before = 0.0;
-            if (any_abs) A_before = fetch_add_complete<AGG>(pend, absorbing);
+            if constexpr (AGG == 2) A_before = fetch_add_complete_wg(pwg, absorbing, wg);
+            else if (any_abs) A_before = fetch_add_complete<AGG>(pend, absorbing);
 
             // re-emission: a* uniform in the package's slice [A_before, A_before + E] / M
             // selects the G(T) bin whose difference spectrum is drawn.  A slice almost
@@ -840,11 +921,18 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
             st = (st == ST_FLY && !__builtin_amdgcn_inverse_ballot_w64(fly)) ? (int)ST_EVT : st;
             lc.steps += sweep_steps;
         }
-        // nothing in flight, nothing parked: all packages done
-        if (__ballot(st != ST_DONE && st != ST_FLY) == 0) break;
+        // nothing in flight, nothing parked: all packages done (with workgroup
+        // grouping, the waves of the workgroup run their passes together until
+        // every wave is done)
+        const bool busy = __ballot(st != ST_DONE && st != ST_FLY) != 0;
+        if constexpr (AGG == 2) {
+            if (!__syncthreads_or(busy ? 1 : 0)) break;
+        } else {
+            if (!busy) break;
+        }
 
         // ---- event batch
-        lc.passes++;
+        if (busy) lc.passes++;
         event_pass();
         cur = P<R>::shell(ps);
         if constexpr (KRHO) curk = rk[ps - sh];
@@ -915,7 +1003,7 @@ __device__ __forceinline__ void single_model(const TraceParams &p, const typenam
     o.k_S = p.k_S;
 }
 
-template <bool AGG, int WT>
+template <int AGG, int WT>
 __global__ __launch_bounds__(kBlockFP32) void ire_trace_f32(TraceParams p) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int nsh = p.n + p.cavity + kSentinels, K = p.K, n_t = p.n_t;
@@ -947,12 +1035,13 @@ __global__ __launch_bounds__(kBlockFP32) void ire_trace_f32(TraceParams p) {
     LaneCounters lc;
     trace_model<float, AGG, WT>(mc, o, s_dust, s_cdf, s_G, s_D, K, n_t, reinterpret_cast<const unsigned char *>(s_guide),
                                 p.g_lg0, p.g_scale, s_rk, &p.stats->cursor, p.chunk,
-                                 p.max_lanes > 0 && gtid >= p.max_lanes, lc, s_sed, s_agg + threadIdx.x / kWave);
+                                 p.max_lanes > 0 && gtid >= p.max_lanes, lc, s_sed, s_agg + threadIdx.x / kWave,
+                                 reinterpret_cast<WgScratch *>(s_agg));
     flush_counters(lc, p.stats);
     flush_sed(s_sed, 4 * K, p.sed);
 }
 
-template <bool AGG, int WT>
+template <int AGG, int WT>
 __global__ __launch_bounds__(256) void ire_trace_f64(TraceParams p) {
     extern __shared__ __align__(16) unsigned char smem[];
     double *s_sed = reinterpret_cast<double *>(smem);
@@ -965,7 +1054,8 @@ __global__ __launch_bounds__(256) void ire_trace_f64(TraceParams p) {
     LaneCounters lc;
     trace_model<double, AGG, WT>(mc, o, p.dustd, p.cdfd, p.Gd, p.Dd, p.K, p.n_t, p.guide, p.g_lg0, p.g_scale,
                                  p.rkd, &p.stats->cursor, p.chunk, p.max_lanes > 0 && gtid >= p.max_lanes, lc, s_sed,
-                                 reinterpret_cast<AggScratch *>(s_sed + 4 * p.K) + threadIdx.x / kWave);
+                                 reinterpret_cast<AggScratch *>(s_sed + 4 * p.K) + threadIdx.x / kWave,
+                                 reinterpret_cast<WgScratch *>(s_sed + 4 * p.K));
     flush_counters(lc, p.stats);
     flush_sed(s_sed, 4 * p.K, p.sed);
 }
@@ -1019,7 +1109,7 @@ __global__ void ire_finalize(FinalizeParams p) {
 // next to the shared dust / G / re-emission tables, traces the range with all
 // its waves (package indices from an LDS cursor), and drains before the next.
 
-template <bool AGG, int WT>
+template <int AGG, int WT>
 __global__ __launch_bounds__(kBlockFP32) void ire_trace_batch(BatchParams p) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ unsigned long long s_item;
@@ -1086,7 +1176,7 @@ __global__ __launch_bounds__(kBlockFP32) void ire_trace_batch(BatchParams p) {
         trace_model<float, AGG, WT>(mc, o, s_dust, s_cdf, s_G, s_D, K, n_t,
                                     reinterpret_cast<const unsigned char *>(s_guide), p.g_lg0, p.g_scale, nullptr,
                                     &s_cursor,
-                                     64ull, false, lc, nullptr, s_agg + threadIdx.x / kWave);
+                                     64ull, false, lc, nullptr, s_agg + threadIdx.x / kWave, nullptr);
     }
     flush_counters(lc, p.stats);
 }
@@ -1135,29 +1225,38 @@ size_t trace_lds_bytes(int n_table, int K, int n_t) {
 
 size_t sed_lds_bytes(int K) { return (size_t)4 * K * sizeof(double); }
 
-static const void *f32_kernel(int aggregate, int wt) {
-    if (wt == 2) return aggregate ? reinterpret_cast<const void *>(&ire_trace_f32<true, 2>)
-                                  : reinterpret_cast<const void *>(&ire_trace_f32<false, 2>);
-    if (wt == 1) return aggregate ? reinterpret_cast<const void *>(&ire_trace_f32<true, 1>)
-                                  : reinterpret_cast<const void *>(&ire_trace_f32<false, 1>);
-    return aggregate ? reinterpret_cast<const void *>(&ire_trace_f32<true, 0>)
-                     : reinterpret_cast<const void *>(&ire_trace_f32<false, 0>);
+template <int WT>
+static const void *f32_kernel_wt(int aggregate) {
+    if (aggregate == 2) return reinterpret_cast<const void *>(&ire_trace_f32<2, WT>);
+    if (aggregate == 1) return reinterpret_cast<const void *>(&ire_trace_f32<1, WT>);
+    return reinterpret_cast<const void *>(&ire_trace_f32<0, WT>);
 }
 
+static const void *f32_kernel(int aggregate, int wt) {
+    if (wt == 2) return f32_kernel_wt<2>(aggregate);
+    if (wt == 1) return f32_kernel_wt<1>(aggregate);
+    return f32_kernel_wt<0>(aggregate);
+}
+
+// the batched launch groups by wave (aggregate 2 is a single-model schedule)
 static const void *batch_kernel(int aggregate, int wt) {
-    if (wt >= 1) return aggregate ? reinterpret_cast<const void *>(&ire_trace_batch<true, 1>)
-                                  : reinterpret_cast<const void *>(&ire_trace_batch<false, 1>);
-    return aggregate ? reinterpret_cast<const void *>(&ire_trace_batch<true, 0>)
-                     : reinterpret_cast<const void *>(&ire_trace_batch<false, 0>);
+    if (wt >= 1) return aggregate ? reinterpret_cast<const void *>(&ire_trace_batch<1, 1>)
+                                  : reinterpret_cast<const void *>(&ire_trace_batch<0, 1>);
+    return aggregate ? reinterpret_cast<const void *>(&ire_trace_batch<1, 0>)
+                     : reinterpret_cast<const void *>(&ire_trace_batch<0, 0>);
+}
+
+template <int WT>
+static const void *f64_kernel_wt(int aggregate) {
+    if (aggregate == 2) return reinterpret_cast<const void *>(&ire_trace_f64<2, WT>);
+    if (aggregate == 1) return reinterpret_cast<const void *>(&ire_trace_f64<1, WT>);
+    return reinterpret_cast<const void *>(&ire_trace_f64<0, WT>);
 }
 
 static const void *f64_kernel(int aggregate, int wt) {
-    if (wt == 2) return aggregate ? reinterpret_cast<const void *>(&ire_trace_f64<true, 2>)
-                                  : reinterpret_cast<const void *>(&ire_trace_f64<false, 2>);
-    if (wt == 1) return aggregate ? reinterpret_cast<const void *>(&ire_trace_f64<true, 1>)
-                                  : reinterpret_cast<const void *>(&ire_trace_f64<false, 1>);
-    return aggregate ? reinterpret_cast<const void *>(&ire_trace_f64<true, 0>)
-                     : reinterpret_cast<const void *>(&ire_trace_f64<false, 0>);
+    if (wt == 2) return f64_kernel_wt<2>(aggregate);
+    if (wt == 1) return f64_kernel_wt<1>(aggregate);
+    return f64_kernel_wt<0>(aggregate);
 }
 
 // The weighted-sampling instantiations are used only when an option needs

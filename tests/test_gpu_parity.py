@@ -55,6 +55,7 @@ def counts(s):
 
 SERIAL_CASES = [
     ("ext50", wl.cfg_external_small, dict(n_ext=3000), {}),
+    ("ext50_workgroup_grouping", wl.cfg_external_small, dict(n_ext=3000), dict(aggregate=2)),
     ("ext50_kbg_ffi", wl.cfg_external_small, dict(n_ext=2000), dict(k_bg=0.2, ffi=1)),
     ("ext101", wl.cfg_external_large, dict(n_ext=800), {}),
     ("central200", wl.cfg_central, dict(n_ps=300), {}),
@@ -153,6 +154,10 @@ def test_parallel_weighted_against_oracle_ensemble(ire, opts):
     ("ext101_1e8_replicas8", wl.cfg_external_large, dict(n_ext=100_000_000), "ext101_tau10_1e7", dict(replicas=8)),
     ("central200_1e8_replicas8", wl.cfg_central, dict(n_ps=100_000_000), "central200_tau100_1e7",
      dict(replicas=8)),
+    # the workgroup-wide grouping of absorptions
+    ("ext101_1e8_workgroup", wl.cfg_external_large, dict(n_ext=100_000_000), "ext101_tau10_1e7", dict(aggregate=2)),
+    ("central200_1e8_workgroup", wl.cfg_central, dict(n_ps=100_000_000), "central200_tau100_1e7",
+     dict(aggregate=2)),
 ])
 def test_full_size_against_1e7_ensemble(ire, name, factory, npk, gold, opts):
     # full-size runs (as benchmarked) against the oracle's 16-seed ensemble at
@@ -167,7 +172,8 @@ def test_full_size_against_1e7_ensemble(ire, name, factory, npk, gold, opts):
 
 
 @pytest.mark.parametrize("opts", [dict(batch=1), dict(batch=32), dict(batch=64), dict(aggregate=0),
-                                  dict(replicas=2, batch=48)])
+                                  dict(aggregate=2), dict(aggregate=2, batch=16), dict(replicas=2, batch=48),
+                                  dict(replicas=2, aggregate=2)])
 def test_schedule_options_do_not_change_results(ire, opts):
     g = golden("ext50_tau1_1e5")
     r = ire.run_model(wl.cfg_external_small(), n_ext=100_000, seed=106, **opts)
@@ -252,7 +258,7 @@ def test_invalid_arguments_rejected(ire):
         assert e.value.code == ire.IRE_E_STATE
         for bad in (dict(k_bg=0.0), dict(k_A=0.0), dict(k_S=float("inf")), dict(use_g_E=1, g_E=1.0),
                     dict(use_g_S=2), dict(ffi=3), dict(k_A_rho=1, k_A=2.0), dict(k_A_rho=1, k_A_lowest=0.0),
-                    dict(replicas=0), dict(replicas=9), dict(replicas=2, max_lanes=1)):
+                    dict(replicas=0), dict(replicas=9), dict(replicas=2, max_lanes=1), dict(aggregate=3)):
             with pytest.raises(ire.IREError) as e:
                 h.set_options(**bad)
             assert e.value.code == ire.IRE_E_INVALID, bad
