@@ -302,7 +302,7 @@ def main() -> int:
     h = ire.IREModel(0)
     h.set_model(model)
     base_opts = dict(batch=int(os.environ.get("IRE_BENCH_BATCH", "0")),
-                     aggregate=int(os.environ.get("IRE_BENCH_AGG", "1")), replicas=args.replicas)
+                     aggregate=int(os.environ.get("IRE_BENCH_AGG", "-1")), replicas=args.replicas)
     h.set_options(**base_opts)
 
     def step(seed: int):

@@ -57,10 +57,12 @@ typedef struct ire_options {
     int32_t reemit_uniform; /* Sect. 4: re-emit at a uniformly random point of the shell volume (0/1) */
     int32_t aggregate;    /* how the absorptions of a pass are folded before the returning global atomics:
                              0: one atomic per lane; 1: per wave, by shell; 2: per workgroup, by shell (the
-                             workgroup's waves then run their event passes together; fewer than 2^22 shells) */
+                             workgroup's waves then run their event passes together; fewer than 2^22 shells);
+                             -1 (default): 2 with replicas = 1, 1 otherwise */
     int32_t batch;        /* lanes of a wave parked at an event before their events are processed together
-                             (1..64, at most the wave's lanes with packages; 0 = default: 64 with replicas = 1,
-                             32 otherwise); changes speed, not the distribution of results */
+                             (1..64, at most the wave's lanes with packages; 0 = default: 48 with aggregate 2,
+                             else 64 with replicas = 1 and 32 otherwise); changes speed, not the distribution
+                             of results */
     /* Sect. 2.2, Table 1: weighted sampling.  Reference direction: towards the
      * centre for packages of the external field, outwards for the point source. */
     int32_t use_g_E;      /* Eq. 6: re-emission cosine about the reference direction from HG(g_E), g_E in (-1,1) */
@@ -101,7 +103,7 @@ typedef struct ire_stats {
 } ire_stats;
 
 /* Fill *o with the defaults: k_bg 0.5, ffi 0, w_floor 1e-10, max_events 1e6,
- * stepping IRE_FP32, max_lanes 0, reemit_uniform 0, aggregate 1, batch 0,
+ * stepping IRE_FP32, max_lanes 0, reemit_uniform 0, aggregate -1, batch 0,
  * use_g_E 0, g_E 0, use_g_S 0, g_S 0, k_A 1, k_S 1, k_A_rho 0, k_A_lowest 3, k_A_highest 1, replicas 1. */
 int ire_default_options(ire_options *o);
 

@@ -165,7 +165,7 @@ int ire_default_options(ire_options *o) {
     o->stepping = IRE_FP32;
     o->max_lanes = 0;
     o->reemit_uniform = 0;
-    o->aggregate = 1;
+    o->aggregate = -1;
     o->batch = 0;
     o->use_g_E = 0;
     o->g_E = 0.0;
@@ -328,7 +328,7 @@ int ire_set_options(ire_model *m, const ire_options *o) {
         return m->fail(IRE_E_INVALID, "k_A_rho needs k_A = 1 and finite k_A_lowest, k_A_highest > 0");
     if (o->k_A_lowest != m->opt.k_A_lowest || o->k_A_highest != m->opt.k_A_highest) m->dirty = true;
     if (o->reemit_uniform != 0 && o->reemit_uniform != 1) return m->fail(IRE_E_INVALID, "reemit_uniform must be 0 or 1");
-    if (o->aggregate < 0 || o->aggregate > 2) return m->fail(IRE_E_INVALID, "aggregate must be 0, 1 or 2");
+    if (o->aggregate < -1 || o->aggregate > 2) return m->fail(IRE_E_INVALID, "aggregate must be -1, 0, 1 or 2");
     if (o->batch < 0 || o->batch > 64) return m->fail(IRE_E_INVALID, "batch must be in [0, 64]");
     if (o->replicas < 1 || o->replicas > ire::kMaxReplicas)
         return m->fail(IRE_E_INVALID, "replicas must be in [1, %d]", ire::kMaxReplicas);
@@ -378,7 +378,12 @@ int ire_advance(ire_model *m, uint64_t n_ext, uint64_t n_ps, void *hip_stream) {
     if (n_ext + n_ps == 0) return IRE_OK;
     if (m->replicas > 1 && m->opt.max_lanes > 0)
         return m->fail(IRE_E_STATE, "a run begun with replicas > 1 cannot continue with max_lanes > 0");
-    if (m->opt.aggregate == 2 && m->rho.size() >= (1u << 22))
+    // schedule: with one running total per shell the returning atomics bound the launch, and grouping the
+    // absorptions of the whole workgroup (its waves pass together, at 48 parked lanes) makes the fewest
+    // atomics; with accumulator groups the launch is instruction-bound, and per-wave grouping at half the
+    // wave is the better balance
+    const int agg = m->opt.aggregate >= 0 ? m->opt.aggregate : (m->replicas > 1 ? 1 : 2);
+    if (agg == 2 && m->rho.size() >= (1u << 22))
         return m->fail(IRE_E_INVALID, "aggregate = 2 supports fewer than 2^22 shells");
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
     hipError_t e;
@@ -396,7 +401,7 @@ int ire_advance(ire_model *m, uint64_t n_ext, uint64_t n_ps, void *hip_stream) {
         if (lds > m->max_lds)
             return m->fail(IRE_E_INVALID, "FP32 tables need %zu bytes of LDS, the device has %zu; use IRE_FP64",
                            lds, m->max_lds);
-        if ((e = ire::trace_configure(0, m->opt.aggregate, lds)) != hipSuccess) return m->hip_fail(e, "configure tracer");
+        if ((e = ire::trace_configure(0, agg, lds)) != hipSuccess) return m->hip_fail(e, "configure tracer");
         block = ire::trace_block_fp32();
         grid = m->n_cu;
     }
@@ -431,13 +436,10 @@ int ire_advance(ire_model *m, uint64_t n_ext, uint64_t n_ps, void *hip_stream) {
         unsigned long long c = (n_ext + n_ps) / (waves * 8ull);
         p.chunk = std::min<unsigned long long>(std::max<unsigned long long>(c, 64ull), 4096ull);
     }
-    // default event-pass threshold: with one running total per shell the returning atomics bound the
-    // launch, and waiting for every lane groups more absorptions per atomic; with accumulator groups the
-    // launch is instruction-bound and half the wave balances stepping against pass overhead
-    p.batch = m->opt.batch > 0 ? m->opt.batch : (m->replicas > 1 ? 32 : 64);
+    p.batch = m->opt.batch > 0 ? m->opt.batch : (agg == 2 ? 48 : (m->replicas > 1 ? 32 : 64));
     if ((e = ire::launch_zero(nullptr, n, m->stats.p, 0, nullptr, 0, s)) != hipSuccess) return m->hip_fail(e, "cursor reset");
     if ((e = hipEventRecord(m->ev0, s)) != hipSuccess) return m->hip_fail(e, "event");
-    if ((e = ire::launch_trace(p, fp64, m->opt.aggregate, grid, block, lds, s)) != hipSuccess)
+    if ((e = ire::launch_trace(p, fp64, agg, grid, block, lds, s)) != hipSuccess)
         return m->hip_fail(e, "trace launch");
     if ((e = hipEventRecord(m->ev1, s)) != hipSuccess) return m->hip_fail(e, "event");
     m->timed = true;

@@ -31,7 +31,7 @@ def test_options_layout_and_defaults():
     from paper_2408_13807_amd import ire
     o = ire.default_options()
     assert (o.k_bg, o.ffi, o.w_floor, o.max_events, o.stepping, o.max_lanes, o.reemit_uniform,
-            o.aggregate, o.batch) == (0.5, 0, 1e-10, 1000000, 0, 0, 0, 1, 0)
+            o.aggregate, o.batch) == (0.5, 0, 1e-10, 1000000, 0, 0, 0, -1, 0)
     assert (o.use_g_E, o.g_E, o.use_g_S, o.g_S, o.k_A, o.k_S) == (0, 0.0, 0, 0.0, 1.0, 1.0)
     assert (o.k_A_rho, o.k_A_lowest, o.k_A_highest, o.replicas) == (0, 3.0, 1.0, 1)
     b = ire.default_batch_options()
