@@ -34,7 +34,7 @@ VALU_PER_EVENT = {"cross": 18.97, "launch": 289.61, "scat": 284.51, "abs": 339.3
 # HBM bytes per tracer launch from FETCH_SIZE and WRITE_SIZE, scaled by a
 # plain 1 GiB copy (profiles/ire_trace_f32_ext101_tauV10_1e8.md); valid for
 # the tracer as profiled and set to None whenever the kernel changes.
-TRAFFIC_BYTES = {"ext101_tauV10_1e8": 1.851e9}
+TRAFFIC_BYTES = {"ext101_tauV10_1e8": 5.932e8}
 
 # MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = VALU lane-instruction issue peak
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
