@@ -140,3 +140,43 @@ def test_predict_models_rejects_bad_offsets(sur):
             net.predict_models(x, np.array(ro), np.array(ra), r)
         assert e.value.code == ire.IRE_E_INVALID
     net.close()
+
+
+def test_trained_surrogate_gains_over_the_tracer(sur):
+    # End to end on a small parameter study: train the ensemble on batched IRE
+    # temperatures of 8000 study models, then, on 512 held-out models, compare
+    # surrogate-with-fallback against the batched tracer alone, both scored
+    # against IRE at 4x each model's package budget.  The surrogate must keep
+    # the models it accepts close to the reference and answer far faster than
+    # the tracer that trained it.
+    import time
+
+    from paper_2408_13807_amd import workloads as wl
+    train = wl.batch_parameters(8000, seed=11)
+    r = sur.ire_profiles(train, range(8000), package_scale=0.5)
+    X, y = sur.training_set(train, range(8000), r["T"])
+    print(f"training rows {len(y)}", flush=True)
+    net = sur.fit(X, y, steps=8000, batch=4096, seed=3)
+    try:
+        held = wl.batch_parameters(512, seed=12)
+        ref = sur.ire_profiles(held, range(512), package_scale=4.0)
+        own = sur.ire_profiles(held, range(512), package_scale=1.0)
+        sur.predict_models(net, held, range(8))        # warm-up
+        t0 = time.perf_counter()
+        p = sur.predict_models(net, held, range(512))
+        t_pred = time.perf_counter() - t0
+        out = sur.predict_with_fallback(net, held, range(512), threshold=0.02)
+    finally:
+        net.close()
+    acc = p["model_spread"] <= 0.02
+    err_s = sur.model_errors(10.0 ** p["logT"].astype(np.float64), ref["T"], ref["row_off"])
+    err_i = sur.model_errors(own["T"], ref["T"], ref["row_off"])
+    err_f = sur.model_errors(out["T"], ref["T"], ref["row_off"])
+    print(f"accepted {acc.mean():.2f}; median error accepted {np.median(err_s[acc]):.4f}, "
+          f"with fallback {np.median(err_f):.4f}, tracer alone {np.median(err_i):.4f}; "
+          f"prediction {t_pred * 1e3:.1f} ms vs tracer {own['seconds'] * 1e3:.1f} ms", flush=True)
+    assert acc.mean() > 0.3
+    assert np.median(err_s[acc]) < 0.02
+    assert np.mean(err_f <= 0.02) > 0.85
+    # the prediction of every model takes a fraction of what the tracer needs for them
+    assert t_pred < 0.2 * own["seconds"]
