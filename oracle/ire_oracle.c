@@ -48,8 +48,11 @@
  * (seed_lo, seed_hi) and counter (b, p_lo, p_hi, s), b = 0,1,2,... the block
  * index within the package's history.  Launch takes one block (frequency,
  * direction, tau_A or FFI depth, tau_S or FFI event type); a scattering one
- * block (cos theta, azimuth, tau_A, tau_S); an absorption two blocks
- * (slice point, frequency, direction, tau_A | tau_S, re-emission radius).
+ * block (cos theta, azimuth, tau_A, tau_S); an absorption one block
+ * (tau_S, frequency, direction, tau_A) and, in table mode when its slice
+ * reaches across a bin edge of G or when the re-emission radius is redrawn, a
+ * second (tau_S, re-emission radius), the first word then placing the slice
+ * point.
  * The scattering azimuth is measured from the plane that holds the propagation
  * direction and the radius vector.
  */

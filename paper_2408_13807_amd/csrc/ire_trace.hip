@@ -14,8 +14,9 @@
 // the package energy into the shell and re-emits it at once, isotropically, at
 // a frequency drawn from the difference of the shell emission spectra at the new
 // and old temperatures; both free paths are redrawn after every event.
-// Weighting: centre-weighted background directions (Eq. 5) and forced first
-// interaction (Eqs. 9-12).
+// Weighting: centre-weighted background directions (Eq. 5), forced first
+// interaction (Eqs. 9-12), weighted re-emission and scattering directions and
+// scaled free paths (Table 1, Eqs. 6-8), density-dependent absorption scaling.
 //
 // The difference-spectrum draw uses lookup tables: with the cumulative emission
 // taken as linear in G(T) within a temperature bin, drawing a point a* uniformly
@@ -23,12 +24,16 @@
 // in the G table and drawing the frequency from that bin's CDF of
 // kappa_abs [B(T_hi) - B(T_lo)] w reproduces the difference spectrum, and the
 // slices of all absorptions in a shell tile [0, A_final] in any order.  A_before
-// is therefore the value returned by a returning FP64 atomic, optionally after a
-// wave-level segmented scan of the energies of lanes absorbing in the same shell.
+// is therefore the value returned by a returning FP64 atomic; the absorptions of
+// a pass that fall in the same shell share one atomic, grouped per wave or per
+// workgroup (AGG = 1, 2), each lane taking its own offset inside the group's
+// deposit.  With accumulator groups (`replicas`), workgroup b adds into copy
+// b mod R and reads its slices as R times that copy's running total.
 //
 // Random numbers: Philox4x32-10 (Salmon et al. 2011), key = seed, counter =
-// (block, package id lo, package id hi, source); launch and scattering use one
-// block, an absorption two.  u = (x + 0.5) 2^-32.
+// (block, package id lo, package id hi, source); one block per event, a second
+// one for an absorption only when its slice reaches across a bin edge of the
+// G table or the re-emission radius is redrawn.  u = (x + 0.5) 2^-32.
 //
 // Two instantiations: float stepping with all tables in LDS, and double
 // everywhere with tables read from global memory.  Absorbed-energy
