@@ -28,7 +28,7 @@ constexpr int kAggSlots = 32;
 constexpr int kWgSlots = 256;
 __host__ __device__ inline size_t agg_lds_bytes(int block) {
     const size_t wave = (size_t)(block / 64) * kAggSlots * (sizeof(double) + sizeof(int));
-    const size_t wg = (size_t)kWgSlots * (2 * sizeof(double) + sizeof(unsigned));
+    const size_t wg = (size_t)kWgSlots * (2 * sizeof(double) + sizeof(unsigned)) + 2 * sizeof(unsigned);
     return (wave > wg ? wave : wg) + 8;
 }
 // Guide tables (cut-point method, Chen & Asau 1974) accelerate the searches

@@ -197,12 +197,22 @@ struct AggScratch {
     int owner[kAggSlots];
 };
 
-// A workgroup's LDS scratch for grouping the absorptions of all its waves.
+// A workgroup's LDS scratch for grouping the absorptions of all its waves:
+// per slot the key (shell and thread of the owner), the group sum (zero
+// between passes) and the group base; and two words for the workgroup's vote
+// whether any wave still has work, used in alternate passes.
 struct WgScratch {
     double sum[kWgSlots];
     double base[kWgSlots];
     unsigned key[kWgSlots];
+    unsigned busy[2];
 };
+
+// Before the first pass: group sums and votes start at zero.
+__device__ __forceinline__ void wg_scratch_init(WgScratch *wg) {
+    for (int j = threadIdx.x; j < kWgSlots; j += blockDim.x) wg->sum[j] = 0.0;
+    if (threadIdx.x < 2) wg->busy[threadIdx.x] = 0u;
+}
 
 __device__ __forceinline__ double wave_excl_scan(double v) {
     const int lane = __lane_id();
@@ -328,8 +338,7 @@ __device__ __forceinline__ PendingWg fetch_add_issue_wg(double *A, int i, double
     const unsigned kr = act ? wg->key[g.slot] : 0u;
     g.member = act && (int)(kr >> 10) == i;
     g.owner = g.member && (int)(kr & 1023u) == tid;
-    if (g.owner) wg->sum[g.slot] = 0.0;
-    __syncthreads();
+    // the slot's sum is zero here: it starts at zero and its last owner cleared it
     if (g.member) g.off = atomicAdd(&wg->sum[g.slot], E);
     __syncthreads();
     // slot owners deposit their group's total; the rest group within their wave
@@ -371,6 +380,7 @@ __device__ __forceinline__ double fetch_add_complete_wg(const PendingWg &g, bool
     if (g.owner) wg->base[g.slot] = g.w.raw;
     const double wbase = __shfl(g.w.raw, g.w.leader_of, kWave);
     __syncthreads();
+    if (g.owner) wg->sum[g.slot] = 0.0;     // every member has its offset: clear for the next pass
     if (!act) return 0.0;
     return g.member ? wg->base[g.slot] + g.off : wbase + g.w.ex;
 }
@@ -511,6 +521,7 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
     // the event pass reloads its record from `ps`; the LDS pad record below
     // the table keeps such a lane's stale reads in bounds.
     unsigned long long fly = 0;    // wave-uniform
+    int vote = 0;                  // workgroup grouping: the vote word of this pass
     uint32_t sweep_steps = 0;      // moving steps of the current sweep (a sweep ends before 2^32)
     constexpr bool kLoose = std::is_same<R, float>::value;
     auto step = [&]() {
@@ -931,7 +942,14 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
         // every wave is done)
         const bool busy = __ballot(st != ST_DONE && st != ST_FLY) != 0;
         if constexpr (AGG == 2) {
-            if (!__syncthreads_or(busy ? 1 : 0)) break;
+            // the vote of this pass goes to busy[vote]; the other word, used by the
+            // next pass, is cleared once every wave has read it in the previous one
+            if (busy && lane == 0) atomicOr(&wg->busy[vote], 1u);
+            __syncthreads();
+            const bool any = wg->busy[vote] != 0u;
+            if (threadIdx.x == 0) wg->busy[vote ^ 1] = 0u;
+            vote ^= 1;
+            if (!any) break;
         } else {
             if (!busy) break;
         }
@@ -1032,6 +1050,7 @@ __global__ __launch_bounds__(kBlockFP32) void ire_trace_f32(TraceParams p) {
     if constexpr (WT == 2)
         for (int j = threadIdx.x - kPadBelow; j < nsh; j += blockDim.x) s_rk[j] = j < 0 ? float2{0, 0} : p.rkf[j];
     AggScratch *s_agg = reinterpret_cast<AggScratch *>(s_rk + nsh);
+    if constexpr (AGG == 2) wg_scratch_init(reinterpret_cast<WgScratch *>(s_agg));
     __syncthreads();
     ModelCtx<float> mc;
     MethodOpts o;
@@ -1051,6 +1070,7 @@ __global__ __launch_bounds__(256) void ire_trace_f64(TraceParams p) {
     extern __shared__ __align__(16) unsigned char smem[];
     double *s_sed = reinterpret_cast<double *>(smem);
     for (int j = threadIdx.x; j < 4 * p.K; j += blockDim.x) s_sed[j] = 0.0;
+    if constexpr (AGG == 2) wg_scratch_init(reinterpret_cast<WgScratch *>(s_sed + 4 * p.K));
     __syncthreads();
     ModelCtx<double> mc;
     MethodOpts o;
