@@ -318,9 +318,10 @@ __device__ __forceinline__ double fetch_add_complete(const PendingAdd &q, bool a
 // The same for all waves of a workgroup together (aggregate = 2): the lanes of
 // every wave that hit a shell are folded into one deposit, so one atomic per
 // shell and pass leaves the workgroup.  Slots are keyed by shell and thread
-// (shell mod kWgSlots); the lanes whose slot went to another shell fall back
-// to their wave's ballot grouping.  Every thread of the workgroup must call
-// both halves in every pass (they hold workgroup barriers).
+// (shell mod kWgSlots), claimed by the caller before a workgroup barrier; the
+// lanes whose slot went to another shell fall back to their wave's ballot
+// grouping.  Every thread of the workgroup must call both halves in every pass
+// (they hold workgroup barriers).
 struct PendingWg {
     PendingAdd w;          // the wave-level result for the lanes outside the slot groups
     double off = 0.0;      // offset inside the slot group's deposit
@@ -329,12 +330,11 @@ struct PendingWg {
 };
 
 __device__ __forceinline__ PendingWg fetch_add_issue_wg(double *A, int i, double E, bool act, WgScratch *wg) {
+    // every acting lane has written its key ((i << 10) | thread, i < 2^22) to
+    // slot i mod kWgSlots before a workgroup barrier; one key per slot won
     PendingWg g;
     const int tid = (int)threadIdx.x;
     g.slot = i & (kWgSlots - 1);
-    const unsigned key = ((unsigned)i << 10) | (unsigned)tid;   // i < 2^22, tid < 1024
-    if (act) wg->key[g.slot] = key;
-    __syncthreads();
     const unsigned kr = act ? wg->key[g.slot] : 0u;
     g.member = act && (int)(kr >> 10) == i;
     g.owner = g.member && (int)(kr & 1023u) == tid;
@@ -573,14 +573,13 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
     // The event pass: escapes, the event-count limit, refills from the wave's
     // package pool, launches, scatterings and absorptions with immediate
     // re-emission, then new free paths.
-    auto event_pass = [&]() {
-            // ---- event batch
+    // The first part of an event pass: parked packages move to their interaction
+    // points and take the weights of their flights' outcomes.
+    auto pre_event = [&]() {
             if constexpr (kLoose) {
                 cur = P<R>::shell(ps);
                 if constexpr (KRHO) curk = rk[ps - sh];
             }
-            const int i = (int)(ps - sh);        // internal shell index
-            bool absorbing = false, scattering = false;
             // a parked package still stands where its last step began: move it
             // along the column left to the interaction point
             if constexpr (KRHO) {
@@ -618,6 +617,11 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
                 if (!esc) f *= ev_abs ? inv_kA : inv_kS;
                 W *= f;
             }
+    };
+
+    auto event_pass = [&]() {
+            const int i = (int)(ps - sh);        // internal shell index
+            bool absorbing = false, scattering = false;
             if (st == ST_EVT) {
                 if (ps == sentinel) {
                     // the flight left the cloud (the step into the sentinel is no crossing)
@@ -942,6 +946,13 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
         // every wave is done)
         const bool busy = __ballot(st != ST_DONE && st != ST_FLY) != 0;
         if constexpr (AGG == 2) {
+            // the absorptions of this pass claim their slots before the barrier of the
+            // vote (the pass's absorbing lanes, exactly as the event pass decides them)
+            pre_event();
+            if (st == ST_EVT && ps != sentinel && events < o.max_events && ev_abs) {
+                const int ia = (int)(ps - sh) - cav;
+                wg->key[ia & (kWgSlots - 1)] = ((unsigned)ia << 10) | (unsigned)threadIdx.x;
+            }
             // the vote of this pass goes to busy[vote]; the other word, used by the
             // next pass, is cleared once every wave has read it in the previous one
             if (busy && lane == 0) atomicOr(&wg->busy[vote], 1u);
@@ -952,6 +963,7 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
             if (!any) break;
         } else {
             if (!busy) break;
+            pre_event();
         }
 
         // ---- event batch
