@@ -377,7 +377,9 @@ def main() -> int:
         "T_center_K": float(host_res["T"][0]),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
                      "unit": "TOP/s (VALU lane-instructions)", "frac": achieved / VALU_PEAK_TOPS,
-                     "traffic": TRAFFIC_BYTES.get(args.workload)},
+                     "traffic": TRAFFIC_BYTES.get(args.workload) if args.replicas == 1 else None,
+                     "limiter": "returning FP64 atomics on the shells' accumulators (one address per shell)"
+                     if args.replicas == 1 else "VALU issue"},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(model, key, 1_500_000, 16, "same cloud")
