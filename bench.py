@@ -216,7 +216,7 @@ def bench_surrogate(args) -> dict:
         net.predict_models_dev(n_inf, n_rows, mx.data_ptr(), ro.data_ptr(), ra.data_ptr(), rad.data_ptr(),
                                len(q["radius"]), mean.data_ptr(), spread.data_ptr(), mspread.data_ptr(), stream=stream)
     torch.cuda.synchronize()
-    t_pred, t_fb, n_flag = [], [], 0
+    t_pred, t_fb, n_flag, fb = [], [], 0, None
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ts = time.perf_counter()
@@ -229,7 +229,7 @@ def bench_surrogate(args) -> dict:
         say(f"predicted {n_inf} models in {t_pred[-1]:.2f} s; {n_flag} flagged for the IRE fallback")
         tf0 = time.perf_counter()
         if n_flag:
-            S.ire_profiles(pi, flagged, package_scale=1.0, progress=chunks("fallback"))
+            fb = S.ire_profiles(pi, flagged, package_scale=1.0, progress=chunks("fallback"))
         t_fb.append(time.perf_counter() - tf0)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -247,6 +247,7 @@ def bench_surrogate(args) -> dict:
     net.close()
     note.update(inference_models=n_inf, inference_rows=n_rows, predict_s=pred_s,
                 fallback_models=n_flag, fallback_s=sum(t_fb) / len(t_fb),
+                fallback_device_s=fb["device_s"] if fb else 0.0, fallback_events=fb["events"] if fb else None,
                 ire_batched_models_per_s=ire_mps, ire_sample="4096 random models of the same 1e6, one batched launch",
                 speedup_vs_batched_ire=value / ire_mps)
     return {

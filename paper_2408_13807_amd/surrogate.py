@@ -171,6 +171,8 @@ def ire_profiles(params: dict, models, package_scale: float = 1.0, chunk: int = 
     `progress(done, total, seconds)` is called after every launch."""
     models = np.asarray(models, np.int64)
     T, A, secs, pk = [], [], 0.0, 0
+    events = dict.fromkeys(("n_cross", "n_launch", "n_scat", "n_abs"), 0)
+    device_ms = 0.0
     for c0 in range(0, len(models), chunk):
         b = _ire.batch_from_workloads(params, models[c0:c0 + chunk], device=device, package_scale=package_scale)
         if options:
@@ -180,6 +182,9 @@ def ire_profiles(params: dict, models, package_scale: float = 1.0, chunk: int = 
         r = b.results(allow_limit=True)
         secs += time.perf_counter() - t0
         pk += int(r["stats"]["n_launch"])
+        for k in events:
+            events[k] += int(r["stats"][k])
+        device_ms += float(r["stats"]["ms_run"])
         T.append(r["T"])
         A.append(r["A"])
         b.close()
@@ -189,7 +194,7 @@ def ire_profiles(params: dict, models, package_scale: float = 1.0, chunk: int = 
     row_off = np.zeros(len(models) + 1, np.int64)
     np.cumsum(n, out=row_off[1:])
     return dict(T=np.concatenate(T) if T else np.zeros(0), A=np.concatenate(A) if A else np.zeros(0),
-                row_off=row_off, seconds=secs, packages=pk)
+                row_off=row_off, seconds=secs, packages=pk, events=events, device_s=device_ms * 1e-3)
 
 
 def training_set(params: dict, models, T: np.ndarray, t_floor: float = 3.0) -> tuple[np.ndarray, np.ndarray]:
