@@ -299,6 +299,59 @@ def test_empty_and_degenerate_inputs(ire):
     assert r["stats"]["n_launch"] == 77 and r["stats"]["n_escape"] == 77
 
 
+def _binomial_ok(k, n, p, nsig=4.5):
+    return abs(k - n * p) <= nsig * np.sqrt(n * p * (1 - p)) + 1
+
+
+def _fp32_accepts(ire, m):
+    """Whether the FP32 tracer (its tables in LDS) takes the model; a rejection
+    happens before any device work."""
+    with ire.IREModel(0) as h:
+        h.set_model(m)
+        try:
+            h.run(64, 0, 1)
+        except ire.IREError as e:
+            assert e.code == ire.IRE_E_INVALID and "LDS" in str(e)
+            return False
+    return True
+
+
+def test_maximum_shell_count(ire):
+    # the largest cloud whose FP32 tables fit the LDS, found by bisection
+    gray = lambda n, tau, ext: wl.gray_model(n, tau, external=ext, K=8)
+    lo, hi = 1000, 20000
+    assert _fp32_accepts(ire, gray(lo, 1.0, True)) and not _fp32_accepts(ire, gray(hi, 1.0, True))
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        lo, hi = (mid, hi) if _fp32_accepts(ire, gray(mid, 1.0, True)) else (lo, mid)
+    n_max = lo
+    print(f"largest FP32 cloud: {n_max} shells", flush=True)
+    # at that size, the closed forms of a gray pure absorber (uniform sphere):
+    # external field, cosine density 2 mu and chords 2 R mu
+    N = 4_000_000
+    tau = 1.5
+    m = gray(n_max, tau, True)
+    r = ire.run_model(m, n_ext=N, seed=21)
+    s = r["stats"]
+    td = 2 * tau
+    assert _binomial_ok(s["n_direct"], N, 2 * (1 - (1 + td) * np.exp(-td)) / td**2)
+    assert s["n_launch"] == N and s["n_escape"] == N
+    assert abs((sum(s["escaped"]) + s["ffi_escaped"] + s["terminated"]) / s["L_ext"] - 1) < 1e-9
+    assert np.all(r["A"][n_max // 5:] > 0)       # every shell beyond 0.2 R takes tens of absorptions or more
+    # central source: radial transmission e^{-tau}
+    m = gray(n_max, 2.0, False)
+    r = ire.run_model(m, n_ps=N, seed=22)
+    assert _binomial_ok(r["stats"]["n_direct"], N, np.exp(-2.0))
+    assert r["stats"]["n_escape"] == N
+    # one shell more is refused in FP32 and runs with FP64 stepping
+    m = gray(n_max + 1, tau, True)
+    assert not _fp32_accepts(ire, m)
+    N = 200_000
+    r = ire.run_model(m, n_ext=N, seed=23, stepping=ire.IRE_FP64)
+    assert _binomial_ok(r["stats"]["n_direct"], N, 2 * (1 - (1 + td) * np.exp(-td)) / td**2)
+    assert r["stats"]["n_escape"] == N
+
+
 def test_results_into_device_memory(ire):
     import torch
     m = wl.cfg_external_small()
