@@ -34,7 +34,7 @@ VALU_PER_EVENT = {"cross": 18.95, "launch": 292.76, "scat": 285.30, "abs": 340.2
 # HBM bytes per tracer launch from FETCH_SIZE and WRITE_SIZE, scaled by a
 # plain 1 GiB copy (profiles/ire_trace_f32_ext101_tauV10_1e8.md); valid for
 # the tracer as profiled and set to None whenever the kernel changes.
-TRAFFIC_BYTES = {"ext101_tauV10_1e8": 5.932e8}
+TRAFFIC_BYTES = {"ext101_tauV10_1e8": 6.180e8}
 
 # MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = VALU lane-instruction issue peak
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
@@ -303,7 +303,8 @@ def main() -> int:
     h = ire.IREModel(0)
     h.set_model(model)
     base_opts = dict(batch=int(os.environ.get("IRE_BENCH_BATCH", "0")),
-                     aggregate=int(os.environ.get("IRE_BENCH_AGG", "-1")), replicas=args.replicas)
+                     aggregate=int(os.environ.get("IRE_BENCH_AGG", "-1")),
+                     quorum=int(os.environ.get("IRE_BENCH_QUORUM", "0")), replicas=args.replicas)
     h.set_options(**base_opts)
 
     def step(seed: int):
@@ -379,7 +380,8 @@ def main() -> int:
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
                      "unit": "TOP/s (VALU lane-instructions)", "frac": achieved / VALU_PEAK_TOPS,
                      "traffic": TRAFFIC_BYTES.get(args.workload) if args.replicas == 1 else None,
-                     "limiter": "returning FP64 atomics on the shells' accumulators (one address per shell)"
+                     "limiter": "workgroup-wide event passes (barrier waits, parked lanes) that keep the returning "
+                                "FP64 atomics on the shells' accumulators (one address per shell) few"
                      if args.replicas == 1 else "VALU issue"},
     }
     if not args.no_cpu_baseline:

@@ -60,7 +60,7 @@ typedef struct ire_options {
                              workgroup's waves then run their event passes together; fewer than 2^22 shells);
                              -1 (default): 2 with replicas = 1, 1 otherwise */
     int32_t batch;        /* lanes of a wave parked at an event before their events are processed together
-                             (1..64, at most the wave's lanes with packages; 0 = default: 48 with aggregate 2,
+                             (1..64, at most the wave's lanes with packages; 0 = default: 52 with aggregate 2,
                              else 64 with replicas = 1 and 32 otherwise); changes speed, not the distribution
                              of results */
     /* Sect. 2.2, Table 1: weighted sampling.  Reference direction: towards the
@@ -85,6 +85,11 @@ typedef struct ire_options {
                              it estimates the temperatures as the mean of R runs of N/R packages does, with
                              the low-N bias of runs of N/R packages in the innermost cells (Sect. 3.1 finds
                              ~1e8 packages per run enough for ~1 % in every cell).  Needs max_lanes = 0. */
+    int32_t quorum;       /* aggregate = 2 only: once this many of a workgroup's waves have ended their
+                             crossing sweeps at `batch` parked lanes, the others end theirs early and the
+                             workgroup runs its event pass; with `quorum` or fewer waves left with packages
+                             each wave sweeps to its own batch (1..16; 16 = always; 0 = default: 6); changes
+                             speed, not the distribution of results */
 } ire_options;
 
 typedef struct ire_stats {
@@ -104,7 +109,8 @@ typedef struct ire_stats {
 
 /* Fill *o with the defaults: k_bg 0.5, ffi 0, w_floor 1e-10, max_events 1e6,
  * stepping IRE_FP32, max_lanes 0, reemit_uniform 0, aggregate -1, batch 0,
- * use_g_E 0, g_E 0, use_g_S 0, g_S 0, k_A 1, k_S 1, k_A_rho 0, k_A_lowest 3, k_A_highest 1, replicas 1. */
+ * use_g_E 0, g_E 0, use_g_S 0, g_S 0, k_A 1, k_S 1, k_A_rho 0, k_A_lowest 3, k_A_highest 1, replicas 1,
+ * quorum 0. */
 int ire_default_options(ire_options *o);
 
 /* Create a handle bound to HIP device `hip_device`; *out is owned by the caller

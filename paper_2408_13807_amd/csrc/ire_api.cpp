@@ -177,6 +177,7 @@ int ire_default_options(ire_options *o) {
     o->k_A_lowest = 3.0;
     o->k_A_highest = 1.0;
     o->replicas = 1;
+    o->quorum = 0;
     return IRE_OK;
 }
 
@@ -333,6 +334,7 @@ int ire_set_options(ire_model *m, const ire_options *o) {
     if (o->replicas < 1 || o->replicas > ire::kMaxReplicas)
         return m->fail(IRE_E_INVALID, "replicas must be in [1, %d]", ire::kMaxReplicas);
     if (o->replicas > 1 && o->max_lanes > 0) return m->fail(IRE_E_INVALID, "replicas > 1 needs max_lanes = 0");
+    if (o->quorum < 0 || o->quorum > 16) return m->fail(IRE_E_INVALID, "quorum must be in [0, 16]");
     m->opt = *o;
     return IRE_OK;
 }
@@ -378,10 +380,10 @@ int ire_advance(ire_model *m, uint64_t n_ext, uint64_t n_ps, void *hip_stream) {
     if (n_ext + n_ps == 0) return IRE_OK;
     if (m->replicas > 1 && m->opt.max_lanes > 0)
         return m->fail(IRE_E_STATE, "a run begun with replicas > 1 cannot continue with max_lanes > 0");
-    // schedule: with one running total per shell the returning atomics bound the launch, and grouping the
-    // absorptions of the whole workgroup (its waves pass together, at 48 parked lanes) makes the fewest
-    // atomics; with accumulator groups the launch is instruction-bound, and per-wave grouping at half the
-    // wave is the better balance
+    // schedule: with one running total per shell, per-lane or per-wave atomics on the few addresses bound
+    // the launch, and grouping the absorptions of the whole workgroup (its waves pass together, at 52 parked
+    // lanes, or once 6 waves are there) makes the fewest; with accumulator groups the launch is
+    // instruction-bound, and per-wave grouping at half the wave is the better balance
     const int agg = m->opt.aggregate >= 0 ? m->opt.aggregate : (m->replicas > 1 ? 1 : 2);
     if (agg == 2 && m->rho.size() >= (1u << 22))
         return m->fail(IRE_E_INVALID, "aggregate = 2 supports fewer than 2^22 shells");
@@ -436,7 +438,8 @@ int ire_advance(ire_model *m, uint64_t n_ext, uint64_t n_ps, void *hip_stream) {
         unsigned long long c = (n_ext + n_ps) / (waves * 8ull);
         p.chunk = std::min<unsigned long long>(std::max<unsigned long long>(c, 64ull), 4096ull);
     }
-    p.batch = m->opt.batch > 0 ? m->opt.batch : (agg == 2 ? 48 : (m->replicas > 1 ? 32 : 64));
+    p.batch = m->opt.batch > 0 ? m->opt.batch : (agg == 2 ? 52 : (m->replicas > 1 ? 32 : 64));
+    p.quorum = m->opt.quorum > 0 ? m->opt.quorum : 6;
     if ((e = ire::launch_zero(nullptr, n, m->stats.p, 0, nullptr, 0, s)) != hipSuccess) return m->hip_fail(e, "cursor reset");
     if ((e = hipEventRecord(m->ev0, s)) != hipSuccess) return m->hip_fail(e, "event");
     if ((e = ire::launch_trace(p, fp64, agg, grid, block, lds, s)) != hipSuccess)

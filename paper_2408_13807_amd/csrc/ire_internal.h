@@ -28,7 +28,7 @@ constexpr int kAggSlots = 32;
 constexpr int kWgSlots = 256;
 __host__ __device__ inline size_t agg_lds_bytes(int block) {
     const size_t wave = (size_t)(block / 64) * kAggSlots * (sizeof(double) + sizeof(int));
-    const size_t wg = (size_t)kWgSlots * (2 * sizeof(double) + sizeof(unsigned)) + 2 * sizeof(unsigned);
+    const size_t wg = (size_t)kWgSlots * (2 * sizeof(double) + sizeof(unsigned)) + 4 * sizeof(unsigned);
     return (wave > wg ? wave : wg) + 8;
 }
 // Guide tables (cut-point method, Chen & Asau 1974) accelerate the searches
@@ -102,6 +102,7 @@ struct TraceParams {
     int replicas;                     // accumulator groups: workgroup b adds into copy b % replicas
     unsigned long long chunk;         // package indices a wave takes from the cursor at once (>= 64)
     int batch;                        // parked lanes that trigger an event pass (1..64)
+    int quorum;                       // workgroup grouping: waves at their batch that end every wave's sweep
     double *A;                        // n accumulators, stride kAccStride
     double *sed;                      // 4*K: escaped power per source and frequency, then its unscattered part
     DevStats *stats;

@@ -199,19 +199,24 @@ struct AggScratch {
 
 // A workgroup's LDS scratch for grouping the absorptions of all its waves:
 // per slot the key (shell and thread of the owner), the group sum (zero
-// between passes) and the group base; and two words for the workgroup's vote
-// whether any wave still has work, used in alternate passes.
+// between passes) and the group base; two words for the workgroup's vote
+// whether any wave still has work, used in alternate passes; and the quorum
+// word: waves that ended the current sweep (low half, cleared every pass) and
+// waves without packages left (high half).
 struct WgScratch {
     double sum[kWgSlots];
     double base[kWgSlots];
     unsigned key[kWgSlots];
     unsigned busy[2];
+    unsigned quorum;
+    unsigned pad_;
 };
 
-// Before the first pass: group sums and votes start at zero.
+// Before the first pass: group sums, votes and the quorum word start at zero.
 __device__ __forceinline__ void wg_scratch_init(WgScratch *wg) {
     for (int j = threadIdx.x; j < kWgSlots; j += blockDim.x) wg->sum[j] = 0.0;
     if (threadIdx.x < 2) wg->busy[threadIdx.x] = 0u;
+    if (threadIdx.x == 2) wg->quorum = 0u;
 }
 
 __device__ __forceinline__ double wave_excl_scan(double v) {
@@ -430,6 +435,7 @@ struct ModelCtx {
 struct MethodOpts {
     double k_bg;
     int ffi, reemit_uniform, batch;
+    int quorum;                      // workgroup grouping: see the crossing sweep
     double w_floor;
     unsigned long long max_events;
     // weighted sampling (Table 1): HG re-emission / scattering directions
@@ -919,27 +925,54 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
             }
     };
 
+    // workgroup grouping: the waves of the workgroup; the quorum word's high half
+    // counts those without packages left
+    const int n_waves = (int)(blockDim.x / kWave);
+    bool wave_done = false;
     for (;;) {
         // ---- crossing sweep: packages in flight step from boundary to boundary;
         // a package that reaches its interaction parks, and the wave stops stepping
         // when enough of its packages are parked to process their events together.
-        // Four steps per check: a step of a parked package changes nothing.
+        // Four steps per check: a step of a parked package changes nothing.  With
+        // workgroup grouping every wave waits for the others at the pass, so a
+        // wave also stops once `quorum` of the waves that still have packages have
+        // ended their sweeps (a wave counts itself only after its own sweep, so
+        // at least one wave always ends by its own count).
         {
             const int live = __popcll(__ballot(st != ST_DONE));
             const int want = batch < live ? batch : (live > 0 ? live : 1);
             fly = __ballot(st == ST_FLY);
             sweep_steps = 0;
+            if constexpr (AGG == 2) {
+                if (live == 0 && !wave_done) {
+                    wave_done = true;
+                    if (lane == 0) atomicAdd(&wg->quorum, 1u << 16);
+                }
+            }
+            bool stop = false;
             for (;;) {
                 const int nfly = __popcll(fly);
-                if (nfly == 0 || live - nfly >= want) break;
+                if (nfly == 0 || live - nfly >= want || stop) break;
+                unsigned qw = 0;
+                if constexpr (AGG == 2) qw = __hip_atomic_load(&wg->quorum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 step();
                 step();
                 step();
                 step();
                 lc.slots += 4 * kWave;
+                if constexpr (AGG == 2) {
+                    // with `quorum` or fewer waves left with packages the count is never
+                    // reached (the others can end at most with_pkgs - 1 sweeps)
+                    qw = __builtin_amdgcn_readfirstlane(qw);
+                    const int with_pkgs = n_waves - (int)(qw >> 16);
+                    stop = (int)(qw & 0xffffu) >= (o.quorum < with_pkgs ? o.quorum : with_pkgs);
+                }
             }
             st = (st == ST_FLY && !__builtin_amdgcn_inverse_ballot_w64(fly)) ? (int)ST_EVT : st;
             lc.steps += sweep_steps;
+            if constexpr (AGG == 2) {
+                if (!wave_done && lane == 0) atomicAdd(&wg->quorum, 1u);
+            }
         }
         // nothing in flight, nothing parked: all packages done (with workgroup
         // grouping, the waves of the workgroup run their passes together until
@@ -958,7 +991,12 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
             if (busy && lane == 0) atomicOr(&wg->busy[vote], 1u);
             __syncthreads();
             const bool any = wg->busy[vote] != 0u;
-            if (threadIdx.x == 0) wg->busy[vote ^ 1] = 0u;
+            if (threadIdx.x == 0) {
+                wg->busy[vote ^ 1] = 0u;
+                // every wave has ended its sweep; the next sweeps begin after the
+                // event pass's workgroup barriers
+                atomicAnd(&wg->quorum, 0xffff0000u);
+            }
             vote ^= 1;
             if (!any) break;
         } else {
@@ -1028,6 +1066,7 @@ __device__ __forceinline__ void single_model(const TraceParams &p, const typenam
     o.ffi = p.ffi;
     o.reemit_uniform = p.reemit_uniform;
     o.batch = p.batch;
+    o.quorum = p.quorum;
     o.w_floor = p.w_floor;
     o.max_events = p.max_events;
     o.use_g_E = p.use_g_E;
@@ -1173,6 +1212,7 @@ __global__ __launch_bounds__(kBlockFP32) void ire_trace_batch(BatchParams p) {
     o.ffi = p.ffi;
     o.reemit_uniform = p.reemit_uniform;
     o.batch = p.batch;
+    o.quorum = 16;
     o.w_floor = p.w_floor;
     o.max_events = p.max_events;
     o.use_g_E = p.use_g_E;

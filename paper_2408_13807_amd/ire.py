@@ -41,7 +41,7 @@ class Options(ct.Structure):
                 ("reemit_uniform", ct.c_int32), ("aggregate", ct.c_int32), ("batch", ct.c_int32),
                 ("use_g_E", ct.c_int32), ("g_E", ct.c_double), ("use_g_S", ct.c_int32), ("g_S", ct.c_double),
                 ("k_A", ct.c_double), ("k_S", ct.c_double), ("k_A_rho", ct.c_int32), ("k_A_lowest", ct.c_double),
-                ("k_A_highest", ct.c_double), ("replicas", ct.c_int32)]
+                ("k_A_highest", ct.c_double), ("replicas", ct.c_int32), ("quorum", ct.c_int32)]
 
 
 class Stats(ct.Structure):

@@ -33,7 +33,7 @@ def test_options_layout_and_defaults():
     assert (o.k_bg, o.ffi, o.w_floor, o.max_events, o.stepping, o.max_lanes, o.reemit_uniform,
             o.aggregate, o.batch) == (0.5, 0, 1e-10, 1000000, 0, 0, 0, -1, 0)
     assert (o.use_g_E, o.g_E, o.use_g_S, o.g_S, o.k_A, o.k_S) == (0, 0.0, 0, 0.0, 1.0, 1.0)
-    assert (o.k_A_rho, o.k_A_lowest, o.k_A_highest, o.replicas) == (0, 3.0, 1.0, 1)
+    assert (o.k_A_rho, o.k_A_lowest, o.k_A_highest, o.replicas, o.quorum) == (0, 3.0, 1.0, 1, 0)
     b = ire.default_batch_options()
     assert (b.use_g_E, b.g_E, b.use_g_S, b.g_S, b.k_A, b.k_S, b.use_graph) == (0, 0.0, 0, 0.0, 1.0, 1.0, 1)
 

@@ -173,7 +173,8 @@ def test_full_size_against_1e7_ensemble(ire, name, factory, npk, gold, opts):
 
 @pytest.mark.parametrize("opts", [dict(batch=1), dict(batch=32), dict(batch=64), dict(aggregate=0),
                                   dict(aggregate=2), dict(aggregate=2, batch=16), dict(replicas=2, batch=48),
-                                  dict(replicas=2, aggregate=2)])
+                                  dict(replicas=2, aggregate=2), dict(aggregate=2, quorum=1),
+                                  dict(aggregate=2, quorum=16), dict(aggregate=2, quorum=4, batch=64)])
 def test_schedule_options_do_not_change_results(ire, opts):
     g = golden("ext50_tau1_1e5")
     r = ire.run_model(wl.cfg_external_small(), n_ext=100_000, seed=106, **opts)
@@ -258,7 +259,8 @@ def test_invalid_arguments_rejected(ire):
         assert e.value.code == ire.IRE_E_STATE
         for bad in (dict(k_bg=0.0), dict(k_A=0.0), dict(k_S=float("inf")), dict(use_g_E=1, g_E=1.0),
                     dict(use_g_S=2), dict(ffi=3), dict(k_A_rho=1, k_A=2.0), dict(k_A_rho=1, k_A_lowest=0.0),
-                    dict(replicas=0), dict(replicas=9), dict(replicas=2, max_lanes=1), dict(aggregate=3)):
+                    dict(replicas=0), dict(replicas=9), dict(replicas=2, max_lanes=1), dict(aggregate=3),
+                    dict(quorum=-1), dict(quorum=17)):
             with pytest.raises(ire.IREError) as e:
                 h.set_options(**bad)
             assert e.value.code == ire.IRE_E_INVALID, bad
