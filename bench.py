@@ -272,6 +272,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--replicas", type=int, default=1,
                     help="accumulator groups of the timed single-model launch (1: one running total per shell)")
+    ap.add_argument("--tune", action="store_true",
+                    help="time candidate event-pass schedules on the cloud first and use the fastest")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the weighted and replica variants (profiling runs of the default launch)")
     args = ap.parse_args()
@@ -306,6 +308,12 @@ def main() -> int:
                      aggregate=int(os.environ.get("IRE_BENCH_AGG", "-1")),
                      quorum=int(os.environ.get("IRE_BENCH_QUORUM", "0")), replicas=args.replicas)
     h.set_options(**base_opts)
+    if args.tune:
+        # event-pass schedule timed on this cloud before the warm-up (a sample of the run)
+        q, b = h.tune_schedule(**{key: n_pkg})
+        base_opts.update(quorum=q, batch=b)
+    schedule = {"tuned": bool(args.tune), "quorum": base_opts["quorum"] or "default",
+                "parked_lanes": base_opts["batch"] or "default"}
 
     def step(seed: int):
         h.run(seed=seed, stream=stream, **{key: n_pkg})
@@ -370,7 +378,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": desc, "shells": n, "packages": n_pkg,
                    "stepping": "fp32", "accumulators": "fp64", "accumulator_groups": args.replicas,
-                   "parallelism": "single GPU"},
+                   "event_pass_schedule": schedule, "parallelism": "single GPU"},
         "kernel_ms_avg": k_ms,
         "kernel_packages_per_s": n_pkg / (k_ms * 1e-3),
         "events_per_launch": per_launch,

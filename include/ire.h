@@ -158,6 +158,17 @@ int ire_advance(ire_model *m, uint64_t n_ext, uint64_t n_ps, void *hip_stream);
 /* Zero the accumulators and counters of the current run. */
 int ire_reset(ire_model *m);
 
+/* Pick the event-pass schedule for this model: time one launch of min(n, 2e7)
+ * packages per source (same proportions as n_ext : n_ps) for every candidate
+ * (with workgroup grouping in FP32: quorum 3, 4, 6, 8 x parked lanes 36, 44,
+ * 52; otherwise parked lanes 24, 32, 48, 64), after one untimed launch, and
+ * set the fastest in the handle's options (the other options are kept).
+ * Schedules change speed, not the distribution of results.  *quorum and *batch
+ * (either may be NULL) receive the choice; the tuning runs synchronously on
+ * the null stream and leaves no run begun (call ire_run next).  IRE_E_INVALID
+ * for n_ext + n_ps = 0 or max_lanes > 0. */
+int ire_tune_schedule(ire_model *m, uint64_t n_ext, uint64_t n_ps, int32_t *quorum, int32_t *batch);
+
 /* Wait for queued work of this handle. */
 int ire_sync(ire_model *m);
 

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "ire.h"
@@ -462,6 +463,54 @@ int ire_reset(ire_model *m) {
     if (!m) return IRE_E_INVALID;
     if (!m->begun) return IRE_OK;
     return ire_begin(m, m->n_total[0], m->n_total[1], m->seed);
+}
+
+int ire_tune_schedule(ire_model *m, uint64_t n_ext, uint64_t n_ps, int32_t *quorum, int32_t *batch) {
+    if (!m) return IRE_E_INVALID;
+    if (n_ext + n_ps == 0) return m->fail(IRE_E_INVALID, "no packages to tune with");
+    if (m->opt.max_lanes > 0) return m->fail(IRE_E_INVALID, "tuning needs max_lanes = 0");
+    // a sample of at most 2e7 packages in the run's proportions
+    const double cap = 2e7, tot = (double)n_ext + (double)n_ps;
+    const double f = tot > cap ? cap / tot : 1.0;
+    uint64_t ne = (uint64_t)((double)n_ext * f), np = (uint64_t)((double)n_ps * f);
+    if (n_ext && !ne) ne = 1;
+    if (n_ps && !np) np = 1;
+    const int agg = m->opt.aggregate >= 0 ? m->opt.aggregate : (m->opt.replicas > 1 ? 1 : 2);
+    std::vector<std::pair<int, int>> cand;   // (quorum, batch)
+    if (agg == 2 && m->opt.stepping == IRE_FP32) {
+        for (int q : {3, 4, 6, 8})
+            for (int b : {36, 44, 52}) cand.emplace_back(q, b);
+    } else {
+        for (int b : {24, 32, 48, 64}) cand.emplace_back(m->opt.quorum, b);
+    }
+    const ire_options keep = m->opt;
+    float best_ms = -1.0f;
+    std::pair<int, int> best = cand[0];
+    int rc = IRE_OK;
+    for (size_t c = 0; c <= cand.size() && rc == IRE_OK; ++c) {
+        // candidate 0 runs twice: the first launch is not timed
+        const auto &qb = cand[c == 0 ? 0 : c - 1];
+        m->opt.quorum = qb.first;
+        m->opt.batch = qb.second;
+        if ((rc = ire_begin(m, ne, np, 1)) != IRE_OK || (rc = ire_advance(m, ne, np, nullptr)) != IRE_OK) break;
+        hipError_t e;
+        if ((e = hipEventSynchronize(m->ev1)) != hipSuccess) { rc = m->hip_fail(e, "tuning launch"); break; }
+        float ms = 0.0f;
+        if ((e = hipEventElapsedTime(&ms, m->ev0, m->ev1)) != hipSuccess) { rc = m->hip_fail(e, "tuning timer"); break; }
+        if (c > 0 && (best_ms < 0.0f || ms < best_ms)) {
+            best_ms = ms;
+            best = qb;
+        }
+    }
+    m->opt = keep;
+    m->begun = false;
+    m->timed = false;
+    if (rc != IRE_OK) return rc;
+    m->opt.quorum = best.first;
+    m->opt.batch = best.second;
+    if (quorum) *quorum = best.first;
+    if (batch) *batch = best.second;
+    return IRE_OK;
 }
 
 int ire_sync(ire_model *m) {

@@ -25,7 +25,7 @@ IRE_FP64 = 1
 # every symbol include/ire.h declares
 EXPORTS = ("ire_default_options", "ire_create", "ire_destroy", "ire_set_shells", "ire_set_dust",
            "ire_set_temperature_grid", "ire_set_external_field", "ire_set_point_source",
-           "ire_set_options", "ire_run", "ire_begin", "ire_advance", "ire_reset", "ire_sync",
+           "ire_set_options", "ire_run", "ire_begin", "ire_advance", "ire_reset", "ire_tune_schedule", "ire_sync",
            "ire_get_results", "ire_get_stats", "ire_get_results_dev", "ire_get_sed", "ire_last_error", "ire_planck",
            "ire_batch_default_options", "ire_batch_create", "ire_batch_destroy", "ire_batch_set_dust",
            "ire_batch_set_temperature_grid", "ire_batch_set_sources", "ire_batch_set_models",
@@ -114,6 +114,7 @@ _lib.ire_run.argtypes = [_H, ct.c_uint64, ct.c_uint64, ct.c_uint64, ct.c_void_p]
 _lib.ire_begin.argtypes = [_H, ct.c_uint64, ct.c_uint64, ct.c_uint64]
 _lib.ire_advance.argtypes = [_H, ct.c_uint64, ct.c_uint64, ct.c_void_p]
 _lib.ire_reset.argtypes = [_H]
+_lib.ire_tune_schedule.argtypes = [_H, ct.c_uint64, ct.c_uint64, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32)]
 _lib.ire_sync.argtypes = [_H]
 _lib.ire_get_results.argtypes = [_H, _DP, _DP, ct.POINTER(Stats)]
 _lib.ire_get_stats.argtypes = [_H, ct.POINTER(Stats)]
@@ -251,6 +252,13 @@ class IREModel:
 
     def reset(self):
         self._check(_lib.ire_reset(self._h))
+
+    def tune_schedule(self, n_ext: int = 0, n_ps: int = 0) -> tuple[int, int]:
+        """Time candidate event-pass schedules on this model and keep the fastest;
+        returns (quorum, batch)."""
+        q, b = ct.c_int32(), ct.c_int32()
+        self._check(_lib.ire_tune_schedule(self._h, int(n_ext), int(n_ps), ct.byref(q), ct.byref(b)))
+        return q.value, b.value
 
     def sync(self):
         self._check(_lib.ire_sync(self._h))

@@ -188,6 +188,43 @@ def test_schedule_options_do_not_change_results(ire, opts):
     assert 0 < s["n_cross"] <= s["n_step_slots"]
 
 
+def test_tuned_schedule(ire):
+    # the tuner picks one of its candidates, leaves no run begun, and the tuned
+    # run keeps the oracle ensemble's distribution
+    g = golden("ext50_tau1_1e5")
+    m = wl.cfg_external_small()
+    with ire.IREModel(0) as h:
+        h.set_model(m)
+        q, b = h.tune_schedule(n_ext=2_000_000)
+        assert q in (3, 4, 6, 8) and b in (36, 44, 52), (q, b)
+        with pytest.raises(ire.IREError) as e:
+            h.results()
+        assert e.value.code == ire.IRE_E_STATE
+        h.run(100_000, 0, 106)
+        r = h.results()
+        assert_ensemble_parity(r["T"], g, name=f"ext50 tuned quorum {q} batch {b}")
+        assert r["stats"]["n_launch"] == 100_000
+        with pytest.raises(ire.IREError) as e:
+            h.tune_schedule(0, 0)
+        assert e.value.code == ire.IRE_E_INVALID
+        h.set_options(max_lanes=1)
+        with pytest.raises(ire.IREError) as e:
+            h.tune_schedule(n_ext=1000)
+        assert e.value.code == ire.IRE_E_INVALID
+        # per-wave grouping with accumulator groups: only the parked lanes are tuned
+        h.set_options(replicas=2)
+        q2, b2 = h.tune_schedule(n_ext=1_000_000)
+        assert q2 == 0 and b2 in (24, 32, 48, 64)
+        h.run(100_000, 0, 106)
+        assert_ensemble_parity(h.results()["T"], g, name=f"ext50 replicas 2 tuned batch {b2}")
+    # the central cloud, whose best schedule differs from the defaults
+    with ire.IREModel(0) as h:
+        h.set_model(wl.cfg_central())
+        q, b = h.tune_schedule(n_ps=20_000_000)
+        print(f"central cloud: quorum {q}, {b} parked lanes", flush=True)
+        assert q in (3, 4, 6, 8) and b in (36, 44, 52)
+
+
 def test_parallel_sed_against_oracle_ensemble(ire):
     # the escaping spectrum of the parallel FP32 path against the oracle's
     # 16-seed ensemble, per frequency where the oracle's spectrum is well
