@@ -526,6 +526,19 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
     // current one in every lane: a lane that did not move stops flying, and
     // the event pass reloads its record from `ps`; the LDS pad record below
     // the table keeps such a lane's stale reads in bounds.
+    // FFI: the extinction column (per unit kappa) of the ray from the centre to the
+    // surface, the first flight of every point-source package, summed once here in
+    // the order of an outward walk through the shells
+    R col_centre = 0;
+    if (o.ffi && mc.n_ps > 0) {
+        R r_in = 0;
+        for (const Shell *q = sh; q < sentinel; ++q) {
+            const Shell s = *q;
+            const R r_out = P<R>::sqrt_(s.r2_out);
+            col_centre += s.rho * (r_out - r_in);
+            r_in = r_out;
+        }
+    }
     unsigned long long fly = 0;    // wave-uniform
     int vote = 0;                  // workgroup grouping: the vote word of this pass
     uint32_t sweep_steps = 0;      // moving steps of the current sweep (a sweep ends before 2^32)
@@ -823,9 +836,9 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
                 if (o.ffi) {
                     // extinction optical depth along the whole first ray.  Its shells are
                     // known in advance (inward from the surface down to the shell of the
-                    // tangent point and out again; outward from the centre), so each record
-                    // is requested one shell ahead of its use.  The outward half of an
-                    // inward ray mirrors its inward half.
+                    // tangent point and out again), so each record is requested one shell
+                    // ahead of its use.  The outward half of an inward ray mirrors its
+                    // inward half; the radial ray from the centre is the same for all.
                     R col = 0;
                     if (src == 0) {
                         const Shell *q = sentinel - 1;
@@ -845,18 +858,7 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
                         }
                         col *= (R)2;
                     } else {
-                        const Shell *q = sh;
-                        Shell s = *q;
-                        R r_in = 0;
-                        for (;;) {
-                            const Shell nx = *(q + 1 < sentinel ? q + 1 : q);
-                            const R r_out = P<R>::sqrt_(s.r2_out);
-                            col += s.rho * (r_out - r_in);
-                            if (q + 1 == sentinel) break;
-                            r_in = r_out;
-                            s = nx;
-                            ++q;
-                        }
+                        col = col_centre;
                     }
                     const R tau0 = d.kext * col;
                     if (!(tau0 > (R)0)) {
