@@ -510,6 +510,20 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
     // the dust does not scatter); colT is the rho l column the flight has crossed
     R sigA = 0, sigA0 = 0, colT = 0;
 
+    // FFI: the extinction column (per unit kappa) of the ray from the centre to the
+    // surface, the first flight of every point-source package, summed once here in
+    // the order of an outward walk through the shells
+    R col_centre = 0;
+    if (o.ffi && mc.n_ps > 0) {
+        R r_in = 0;
+        for (const Shell *q = sh; q < sentinel; ++q) {
+            const Shell s = *q;
+            const R r_out = P<R>::sqrt_(s.r2_out);
+            col_centre += s.rho * (r_out - r_in);
+            r_in = r_out;
+        }
+    }
+
     // One boundary step of a package in flight (Eq. 4), computed for every
     // lane and committed only where the package is in flight.  Both free
     // paths fall by kappa rho l along a flight, so the one that runs out
@@ -526,19 +540,6 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
     // current one in every lane: a lane that did not move stops flying, and
     // the event pass reloads its record from `ps`; the LDS pad record below
     // the table keeps such a lane's stale reads in bounds.
-    // FFI: the extinction column (per unit kappa) of the ray from the centre to the
-    // surface, the first flight of every point-source package, summed once here in
-    // the order of an outward walk through the shells
-    R col_centre = 0;
-    if (o.ffi && mc.n_ps > 0) {
-        R r_in = 0;
-        for (const Shell *q = sh; q < sentinel; ++q) {
-            const Shell s = *q;
-            const R r_out = P<R>::sqrt_(s.r2_out);
-            col_centre += s.rho * (r_out - r_in);
-            r_in = r_out;
-        }
-    }
     unsigned long long fly = 0;    // wave-uniform
     int vote = 0;                  // workgroup grouping: the vote word of this pass
     uint32_t sweep_steps = 0;      // moving steps of the current sweep (a sweep ends before 2^32)
