@@ -88,8 +88,8 @@ typedef struct ire_options {
     int32_t quorum;       /* aggregate = 2 only: once this many of a workgroup's waves have ended their
                              crossing sweeps at `batch` parked lanes, the others end theirs early and the
                              workgroup runs its event pass; with `quorum` or fewer waves left with packages
-                             each wave sweeps to its own batch (1..16; 16 = always; 0 = default: 6); changes
-                             speed, not the distribution of results */
+                             each wave sweeps to its own batch (1..16; 16: every wave always does; 0 = default:
+                             6); changes speed, not the distribution of results */
 } ire_options;
 
 typedef struct ire_stats {
@@ -158,8 +158,8 @@ int ire_advance(ire_model *m, uint64_t n_ext, uint64_t n_ps, void *hip_stream);
 /* Zero the accumulators and counters of the current run. */
 int ire_reset(ire_model *m);
 
-/* Pick the event-pass schedule for this model: time one launch of min(n, 2e7)
- * packages per source (same proportions as n_ext : n_ps) for every candidate
+/* Pick the event-pass schedule for this model: time one launch of a sample of
+ * the run (at most 2e7 packages in all, split as n_ext : n_ps) for every candidate
  * (with workgroup grouping in FP32: quorum 3, 4, 6, 8 x parked lanes 36, 44,
  * 52; otherwise parked lanes 24, 32, 48, 64), after one untimed launch, and
  * set the fastest in the handle's options (the other options are kept).
