@@ -29,7 +29,7 @@ if ROOT not in sys.path:
 # VALU instructions one lane executes per event on the FP32 tracer's paths
 # (least-squares fit of SQ_INSTS_VALU over one-lane runs of six clouds;
 # profiles/valu_fit_one_lane_clouds.md holds the fit and its command).
-VALU_PER_EVENT = {"cross": 18.95, "launch": 291.76, "scat": 285.30, "abs": 340.29}
+VALU_PER_EVENT = {"cross": 18.95, "launch": 277.61, "scat": 280.96, "abs": 309.27}
 
 # HBM bytes per tracer launch from FETCH_SIZE and WRITE_SIZE, scaled by a
 # plain 1 GiB copy (profiles/ire_trace_f32_ext101_tauV10_1e8.md); valid for

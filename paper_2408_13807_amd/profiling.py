@@ -39,10 +39,10 @@ def valu_cases() -> list[dict]:
              ("ext50_short", wl.cfg_external_small(), dict(n_ext=200))]
     out = []
     for name, m, kw in cases:
-        # one package in flight; wave-level grouping, so that the workgroup's
-        # idle waves do not run event passes beside it (their instructions are
-        # no work of the package)
-        r = ire.run_model(m, seed=1, max_lanes=1, aggregate=1, **kw)
+        # one package in flight and one atomic per absorption: no grouping code,
+        # and the workgroup's idle waves run no event passes beside it (their
+        # instructions are no work of the package)
+        r = ire.run_model(m, seed=1, max_lanes=1, aggregate=0, **kw)
         out.append(dict(name=name, **{k: r["stats"][k] for k in EVENTS}))
     return out
 

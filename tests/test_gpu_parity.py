@@ -180,7 +180,7 @@ def test_schedule_options_do_not_change_results(ire, opts):
     r = ire.run_model(wl.cfg_external_small(), n_ext=100_000, seed=106, **opts)
     assert_ensemble_parity(r["T"], g, name=f"ext50 {opts}")
     # schedule statistics: a pass handles at most a wave's 64 lanes, sweeps run
-    # in groups of four wave-level steps, and a crossing takes one lane slot
+    # in groups of four or eight wave-level steps, and a crossing takes one lane slot
     s = r["stats"]
     events = s["n_launch"] + s["n_scat"] + s["n_abs"]
     assert s["n_pass"] * 64 >= events
