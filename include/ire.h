@@ -61,7 +61,7 @@ typedef struct ire_options {
                              -1 (default): 2 with replicas = 1, 1 otherwise */
     int32_t batch;        /* lanes of a wave parked at an event before their events are processed together
                              (1..64, at most the wave's lanes with packages; 0 = default: 52 with aggregate 2,
-                             else 64 with replicas = 1 and 32 otherwise); changes speed, not the distribution
+                             else 64 with replicas = 1 and 40 otherwise); changes speed, not the distribution
                              of results */
     /* Sect. 2.2, Table 1: weighted sampling.  Reference direction: towards the
      * centre for packages of the external field, outwards for the point source. */

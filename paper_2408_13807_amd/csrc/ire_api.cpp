@@ -384,7 +384,7 @@ int ire_advance(ire_model *m, uint64_t n_ext, uint64_t n_ps, void *hip_stream) {
     // schedule: with one running total per shell, per-lane or per-wave atomics on the few addresses bound
     // the launch, and grouping the absorptions of the whole workgroup (its waves pass together, at 52 parked
     // lanes, or once 6 waves are there) makes the fewest; with accumulator groups the launch is
-    // instruction-bound, and per-wave grouping at half the wave is the better balance
+    // instruction-bound, and per-wave grouping at 40 parked lanes is the better balance
     const int agg = m->opt.aggregate >= 0 ? m->opt.aggregate : (m->replicas > 1 ? 1 : 2);
     if (agg == 2 && m->rho.size() >= (1u << 22))
         return m->fail(IRE_E_INVALID, "aggregate = 2 supports fewer than 2^22 shells");
@@ -439,7 +439,7 @@ int ire_advance(ire_model *m, uint64_t n_ext, uint64_t n_ps, void *hip_stream) {
         unsigned long long c = (n_ext + n_ps) / (waves * 8ull);
         p.chunk = std::min<unsigned long long>(std::max<unsigned long long>(c, 64ull), 4096ull);
     }
-    p.batch = m->opt.batch > 0 ? m->opt.batch : (agg == 2 ? 52 : (m->replicas > 1 ? 32 : 64));
+    p.batch = m->opt.batch > 0 ? m->opt.batch : (agg == 2 ? 52 : (m->replicas > 1 ? 40 : 64));
     p.quorum = m->opt.quorum > 0 ? m->opt.quorum : 6;
     if ((e = ire::launch_zero(nullptr, n, m->stats.p, 0, nullptr, 0, s)) != hipSuccess) return m->hip_fail(e, "cursor reset");
     if ((e = hipEventRecord(m->ev0, s)) != hipSuccess) return m->hip_fail(e, "event");
