@@ -161,7 +161,7 @@ int ire_reset(ire_model *m);
 /* Pick the event-pass schedule for this model: time one launch of a sample of
  * the run (at most 2e7 packages in all, split as n_ext : n_ps) for every candidate
  * (with workgroup grouping in FP32: quorum 3, 4, 6, 8 x parked lanes 36, 44,
- * 52; otherwise parked lanes 24, 32, 48, 64), after one untimed launch, and
+ * 52; otherwise parked lanes 24, 32, 40, 48, 64), after one untimed launch, and
  * set the fastest in the handle's options (the other options are kept).
  * Schedules change speed, not the distribution of results.  *quorum and *batch
  * (either may be NULL) receive the choice; the tuning runs synchronously on

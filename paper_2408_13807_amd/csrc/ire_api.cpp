@@ -481,7 +481,7 @@ int ire_tune_schedule(ire_model *m, uint64_t n_ext, uint64_t n_ps, int32_t *quor
         for (int q : {3, 4, 6, 8})
             for (int b : {36, 44, 52}) cand.emplace_back(q, b);
     } else {
-        for (int b : {24, 32, 48, 64}) cand.emplace_back(m->opt.quorum, b);
+        for (int b : {24, 32, 40, 48, 64}) cand.emplace_back(m->opt.quorum, b);
     }
     const ire_options keep = m->opt;
     float best_ms = -1.0f;
