@@ -53,7 +53,7 @@ class Stats(ct.Structure):
                 ("terminated", ct.c_double)] + [
         (f, ct.c_uint64) for f in ("n_launch", "n_cross", "n_scat", "n_abs", "n_escape",
                                    "n_direct", "n_limit", "n_floor", "n_below", "n_above",
-                                   "n_reemit_above")]
+                                   "n_reemit_above")] + [("terminated_floor", ct.c_double)]
 
 
 _DP = ct.POINTER(ct.c_double)

@@ -48,11 +48,8 @@
  * (seed_lo, seed_hi) and counter (b, p_lo, p_hi, s), b = 0,1,2,... the block
  * index within the package's history.  Launch takes one block (frequency,
  * direction, tau_A or FFI depth, tau_S or FFI event type); a scattering one
- * block (cos theta, azimuth, tau_A, tau_S); an absorption one block
- * (tau_S, frequency, direction, tau_A) and, in table mode when its slice
- * reaches across a bin edge of G or when the re-emission radius is redrawn, a
- * second (tau_S, re-emission radius), the first word then placing the slice
- * point.
+ * block (cos theta, azimuth, tau_A, tau_S); an absorption two blocks, (slice
+ * point a*, frequency, direction, tau_A) and (tau_S, re-emission radius).
  * The scattering azimuth is measured from the plane that holds the propagation
  * direction and the radius vector.
  */
@@ -729,22 +726,17 @@ static void trace_package(const ostate *s, tally_t *t, int src, uint64_t pid, ui
             if (events == 1 && t->first_abs) t->first_abs[i] += E;
             double A_before = acc_read(s, t, i);
             acc_add(s, t, i, E);
-            /* Random numbers: one block (slice position, frequency, direction, tau_A,
-             * tau_S); a second block when the slice position is needed or the
-             * position in the shell is redrawn. */
-            int straddle = 0;
+            /* Random numbers: two blocks, (slice point, frequency, direction,
+             * tau_A) and (tau_S, position in the shell). */
             next_block(&rs, u);
+            next_block(&rs, u2);
             if (s->o.table_mode) {
-                /* the bin of a* uniform in [A_before, A_before + E] / M_i (reading R8): a
-                 * slice inside one bin fixes the bin without a draw; one that reaches
-                 * across a bin edge takes a* from u[0] and tau_S from the second block */
-                const double alo = A_before / s->M[i], ahi = (A_before + E) / s->M[i];
-                int row = bin_below(s->G, m->n_t, alo) + 1;
-                straddle = row < m->n_t && s->G[row] <= ahi;
-                if (straddle) {
-                    next_block(&rs, u2);
-                    row = bin_below(s->G, m->n_t, (A_before + u[0] * E) / s->M[i]) + 1;
-                }
+                /* reading R8: a* uniform in the slice [A_before, A_before + E] / M_i
+                 * selects the temperature bin of the G table whose difference
+                 * spectrum the frequency is drawn from; a* above the last table
+                 * point takes the last bin (counted) */
+                const double astar = (A_before + u[0] * E) / s->M[i];
+                int row = bin_below(s->G, m->n_t, astar) + 1;
                 if (row > m->n_t - 1) { row = m->n_t - 1; t->st.n_reemit_above++; }
                 k = sample_cdf(s->D + (size_t)row * K, K, u[1]);
             } else {
@@ -777,7 +769,6 @@ static void trace_package(const ostate *s, tally_t *t, int src, uint64_t pid, ui
             if (r > 0.0) { for (int j = 0; j < 3; ++j) xh[j] = x[j] / r; }
             else { xh[0] = 0; xh[1] = 0; xh[2] = 1; }
             if (s->o.reemit_uniform) {
-                if (!straddle) next_block(&rs, u2);
                 double r0 = s->R[i], r1 = s->R[i + 1];
                 double rn = cbrt(r0 * r0 * r0 + u2[1] * (r1 * r1 * r1 - r0 * r0 * r0));
                 for (int j = 0; j < 3; ++j) x[j] = rn * xh[j];
@@ -794,7 +785,7 @@ static void trace_package(const ostate *s, tally_t *t, int src, uint64_t pid, ui
             double sn = sqrt(fmax(0.0, 1.0 - mu * mu));
             for (int j = 0; j < 3; ++j) d[j] = mu * xh[j] + sn * e[j];
             tauA = -log(u[3]);
-            tauS = -log(straddle ? u2[0] : u[0]) / kS;
+            tauS = -log(u2[0]) / kS;
             kw = s->kscale;
             tA0 = tauA;
             tS0 = tauS;
@@ -822,6 +813,7 @@ static void trace_package(const ostate *s, tally_t *t, int src, uint64_t pid, ui
         }
         if (W < s->o.w_floor * W0) {
             t->st.terminated += eps * W;
+            t->st.terminated_floor += eps * W;
             t->st.n_floor++;
             return;
         }

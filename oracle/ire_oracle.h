@@ -73,6 +73,7 @@ typedef struct or_stats {
     uint64_t n_launch, n_cross, n_scat, n_abs, n_escape, n_direct, n_limit, n_floor;
     uint64_t n_below, n_above;      /* final temperatures clamped to the table range */
     uint64_t n_reemit_above;        /* table mode: re-emission draws above the last table point */
+    double terminated_floor;        /* the part of `terminated` stopped by the weight floor */
 } or_stats;
 
 void or_default_options(or_options *o);

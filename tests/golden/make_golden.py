@@ -2,6 +2,8 @@
 
 Calls only the oracle (and the seeded workload generator): 16 independent
 seeds per configuration, per-shell mean and standard deviation of T and A.
+The files hold nothing that depends on the machine or the run (no timings), so
+they are reproduced byte for byte by running this script again.
 Usage: python tests/golden/make_golden.py [name ...]
 """
 import json
@@ -39,11 +41,11 @@ def make(name: str) -> str:
                A_mean=e["A"].mean(axis=0).tolist(), A_std=e["A"].std(axis=0, ddof=1).tolist(),
                n_cross=float(np.mean([s["n_cross"] for s in e["stats"]])),
                n_abs=float(np.mean([s["n_abs"] for s in e["stats"]])),
-               n_scat=float(np.mean([s["n_scat"] for s in e["stats"]])),
-               oracle_seconds=time.time() - t0)
+               n_scat=float(np.mean([s["n_scat"] for s in e["stats"]])))
     path = os.path.join(HERE, f"{name}.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
+    print(f"{name}: {time.time() - t0:.1f} s of oracle", flush=True)
     return path
 
 
