@@ -1,0 +1,196 @@
+"""AddressSanitizer and UndefinedBehaviorSanitizer builds of the host code,
+on the CPU: the serial oracle (oracle/ire_oracle.c) and the library's host-side
+table builders (csrc/ire_host.h), each driven through its fast cases by a small
+harness written here.  A sanitizer report aborts the harness (no recovery), so
+a clean exit means no out-of-bounds access, use after free, leak, signed
+overflow, misaligned access or other undefined behaviour on these inputs.  The
+oracle's sanitized results must also equal those of its normal build."""
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2408_13807_amd import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SAN = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g", "-O1"]
+ENV = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:halt_on_error=1",
+           UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
+
+pytestmark = pytest.mark.skipif(shutil.which("gcc") is None or shutil.which("g++") is None,
+                                reason="needs the host compilers")
+
+ORACLE_HARNESS = r'''
+#include <stdio.h>
+#include <stdlib.h>
+#include "ire_oracle.h"
+/* input: doubles [n, K, n_t, t_min, t_max, L_ps, has_J, has_S], r_edges, rho, nu, kabs,
+   albedo, g, [J], [S], then options [k_bg, ffi, w_floor, max_events, table_mode,
+   reemit_uniform, use_g_E, g_E, use_g_S, g_S, k_A, k_S, k_A_rho, n_ext, n_ps, seed] */
+int main(int argc, char **argv) {
+    FILE *f = fopen(argv[1], "rb");
+    if (!f) return 2;
+    double h[8];
+    if (fread(h, sizeof(double), 8, f) != 8) return 2;
+    int n = (int)h[0], K = (int)h[1];
+    size_t cnt = (size_t)(n + 1) + n + 4 * (size_t)K + (h[6] > 0 ? K : 0) + (h[7] > 0 ? K : 0) + 16;
+    double *d = malloc(cnt * sizeof(double));
+    if (fread(d, sizeof(double), cnt, f) != cnt) return 2;
+    fclose(f);
+    double *p = d;
+    or_model m;
+    m.n = n; m.K = K; m.n_t = (int)h[2]; m.t_min = h[3]; m.t_max = h[4]; m.L_ps = h[5];
+    m.r_edges = p; p += n + 1;
+    m.rho = p; p += n;
+    m.nu = p; p += K;
+    m.kabs = p; p += K;
+    m.albedo = p; p += K;
+    m.g = p; p += K;
+    m.J = h[6] > 0 ? p : NULL; if (h[6] > 0) p += K;
+    m.S = h[7] > 0 ? p : NULL; if (h[7] > 0) p += K;
+    or_options o;
+    or_default_options(&o);
+    o.k_bg = p[0]; o.ffi = (int)p[1]; o.w_floor = p[2]; o.max_events = (uint64_t)p[3]; o.table_mode = (int)p[4];
+    o.reemit_uniform = (int)p[5]; o.use_g_E = (int)p[6]; o.g_E = p[7]; o.use_g_S = (int)p[8]; o.g_S = p[9];
+    o.k_A = p[10]; o.k_S = p[11]; o.k_A_rho = (int)p[12];
+    uint64_t n_ext = (uint64_t)p[13], n_ps = (uint64_t)p[14], seed = (uint64_t)p[15];
+    double *A = calloc(n, sizeof(double)), *T = calloc(n, sizeof(double));
+    double *re = calloc((size_t)n * K, sizeof(double)), *fa = calloc(n, sizeof(double));
+    double *sed = calloc(2 * (size_t)K, sizeof(double)), *sd = calloc(2 * (size_t)K, sizeof(double));
+    or_stats st;
+    int rc = or_run(&m, &o, n_ext, n_ps, seed, A, T, &st, re, fa, sed, sd);
+    if (rc) { printf("rc %d\n", rc); return 3; }
+    for (int i = 0; i < n; ++i) printf("%.17g %.17g\n", A[i], T[i]);
+    printf("%llu %llu %llu %llu %llu\n", (unsigned long long)st.n_cross, (unsigned long long)st.n_abs,
+           (unsigned long long)st.n_scat, (unsigned long long)st.n_floor, (unsigned long long)st.n_reemit_above);
+    free(A); free(T); free(re); free(fa); free(sed); free(sd); free(d);
+    return 0;
+}
+'''
+
+HOST_HARNESS = r'''
+#include <cstdio>
+#include <vector>
+#include "ire_host.h"
+using namespace ire;
+using namespace ire::host;
+// dust tables, guides, shell tables and absorption-scaling records for a set of
+// sizes; prints a checksum per case so that the run is not optimised away
+int main() {
+    int cases = 0;
+    double sum = 0.0;
+    for (int K : {1, 2, 7, 64, 255})
+    for (int nt : {2, 3, 101, 512}) {
+        std::vector<double> nu(K), kabs(K), alb(K), g(K);
+        for (int k = 0; k < K; ++k) {
+            nu[k] = 3e11 * std::pow(1e4, K > 1 ? (double)k / (K - 1) : 0.0);
+            kabs[k] = std::pow(nu[k] / 1e14, nu[k] < 1e14 ? 1.8 : 1.0);
+            alb[k] = nu[k] > 3e14 ? 0.5 : 0.0;
+            g[k] = 0.5;
+        }
+        DustTables dt;
+        if (!build_dust_tables(nu, kabs, alb, g, 3.0, 1600.0, nt, dt).empty()) return 4;
+        std::vector<double> cdf(2 * K);
+        cumulative(kabs.data(), K, cdf.data());
+        cumulative(nu.data(), K, cdf.data() + K);
+        std::vector<unsigned char> guide;
+        float lg0 = 0, sc = 0;
+        build_guides(dt, cdf.data(), K, guide, lg0, sc);
+        if (guide.size() != guide_bytes(nt)) return 5;
+        for (double v : dt.G) sum += v;
+        ++cases;
+    }
+    for (int n : {1, 2, 50, 401, 5000})
+    for (int cav = 0; cav < 2; ++cav) {
+        std::vector<double> r(n + 1), rho(n);
+        for (int i = 0; i <= n; ++i) r[i] = (cav ? 1.0 : 0.0) + i;
+        for (int i = 0; i < n; ++i) rho[i] = i % 7 == 3 ? 0.0 : 1.0 / (1.0 + i);
+        if (!check_shells(n, r.data(), rho.data()).empty()) return 6;
+        std::vector<ShellF> sf;
+        std::vector<ShellD> sd;
+        std::vector<double> invM;
+        build_shell_table(r.data(), rho.data(), n, sf, sd, invM);
+        std::vector<float2> rf;
+        std::vector<double2> rd;
+        build_absorption_scaling(r.data(), rho.data(), n, 3.0, 1.0, rf, rd);
+        if ((int)sf.size() != n + cav + kSentinels || rf.size() != sf.size()) return 7;
+        for (double v : invM) sum += v;
+        ++cases;
+    }
+    std::printf("%d %.6g\n", cases, sum);
+    return 0;
+}
+'''
+
+
+def write_model(path, m, n_ext=0, n_ps=0, seed=1, **opts):
+    o = dict(k_bg=0.5, ffi=0, w_floor=1e-10, max_events=1e6, table_mode=1, reemit_uniform=0, use_g_E=0, g_E=0.0,
+             use_g_S=0, g_S=0.0, k_A=1.0, k_S=1.0, k_A_rho=0)
+    o.update(opts)
+    J, S = m.get("J"), m.get("S") if (m.get("L_ps") or 0) > 0 else None
+    parts = [np.array([len(m["rho"]), len(m["nu"]), m["n_t"], m["t_min"], m["t_max"], m.get("L_ps", 0.0) or 0.0,
+                       J is not None, S is not None], float),
+             m["r_edges"], m["rho"], m["nu"], m["kabs"], m["albedo"], m["g"]]
+    parts += [np.asarray(x, float) for x in (J, S) if x is not None]
+    parts.append(np.array([o[k] for k in ("k_bg", "ffi", "w_floor", "max_events", "table_mode", "reemit_uniform",
+                                          "use_g_E", "g_E", "use_g_S", "g_S", "k_A", "k_S", "k_A_rho")]
+                          + [n_ext, n_ps, seed], float))
+    np.concatenate(parts).astype(np.float64).tofile(path)
+
+
+def cases():
+    central = wl.cfg_central()
+    one = dict(central, r_edges=central["r_edges"][[0, -1]], rho=np.array([central["rho"].mean()]), t_max=5.0, n_t=8)
+    return [
+        ("ext50", wl.cfg_external_small(), dict(n_ext=3000)),
+        ("ext50_exact", wl.cfg_external_small(), dict(n_ext=300, table_mode=0)),
+        ("central200_ffi_uniform", central, dict(n_ps=200, ffi=1, reemit_uniform=1)),
+        ("mixed_cavity", dict(wl.gray_model(10, 2.0, external=False, r_in=0.1 * wl.R_OUT),
+                              J=1e-13 * wl.blackbody(wl.frequency_grid(8, 1e12, 1e15), 8000.0)),
+         dict(n_ext=500, n_ps=500)),
+        ("weighted", wl.cfg_external_small(), dict(n_ext=2000, use_g_E=1, g_E=0.4, use_g_S=1, g_S=0.5, k_A=1.5,
+                                                    k_S=0.7, ffi=2, k_bg=0.3)),
+        ("kArho", wl.cfg_external_large(), dict(n_ext=500, k_A_rho=1)),
+        ("floor", wl.gray_model(10, 2.0, external=True), dict(n_ext=2000, k_bg=0.2, use_g_E=1, g_E=0.5,
+                                                              w_floor=0.5, max_events=1)),
+        ("above_table", one, dict(n_ps=2000)),
+        ("odd_grid", dict(wl.external_sphere(n=7, tau_V=3.0, K=5), n_t=3), dict(n_ext=1000)),
+    ]
+
+
+def test_oracle_under_asan_ubsan(tmp_path, orc):
+    src = tmp_path / "oh.c"
+    src.write_text(ORACLE_HARNESS)
+    exe = tmp_path / "oracle_san"
+    subprocess.run(["gcc", "-std=c11", *SAN, "-I", os.path.join(ROOT, "oracle"), str(src),
+                    os.path.join(ROOT, "oracle", "ire_oracle.c"), "-o", str(exe), "-lm"], check=True)
+    for name, m, kw in cases():
+        inp = tmp_path / f"{name}.bin"
+        npk = dict(n_ext=kw.pop("n_ext", 0), n_ps=kw.pop("n_ps", 0))
+        write_model(inp, m, seed=7, **npk, **kw)
+        r = subprocess.run([str(exe), str(inp)], capture_output=True, text=True, env=ENV)
+        assert r.returncode == 0, (name, r.stderr[-3000:])
+        assert "runtime error" not in r.stderr and "Sanitizer" not in r.stderr, (name, r.stderr[-3000:])
+        rows = r.stdout.split("\n")
+        n = len(m["rho"])
+        AT = np.array([[float(x) for x in l.split()] for l in rows[:n]])
+        counts = [int(x) for x in rows[n].split()]
+        ref = orc.run(m, seed=7, **npk, **kw)
+        np.testing.assert_array_equal(AT[:, 0], ref["A"])
+        np.testing.assert_array_equal(AT[:, 1], ref["T"])
+        assert counts == [ref["stats"][k] for k in ("n_cross", "n_abs", "n_scat", "n_floor", "n_reemit_above")]
+
+
+def test_host_table_builders_under_asan_ubsan(tmp_path):
+    src = tmp_path / "hh.cpp"
+    src.write_text(HOST_HARNESS)
+    exe = tmp_path / "host_san"
+    subprocess.run(["g++", "-std=c++17", *SAN, "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include", "-I",
+                    os.path.join(ROOT, "paper_2408_13807_amd", "csrc"), str(src), "-o", str(exe)], check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, env=ENV)
+    assert r.returncode == 0, r.stderr[-3000:]
+    assert "runtime error" not in r.stderr and "Sanitizer" not in r.stderr, r.stderr[-3000:]
+    cases_run = int(r.stdout.split()[0])
+    assert cases_run == 5 * 4 + 5 * 2
