@@ -82,10 +82,7 @@ struct ire_batch {
 namespace {
 
 size_t lds_bytes(const ire_batch *b) {
-    const int K = (int)b->nu.size();
-    return (size_t)(b->max_table + ire::kPadBelow) * sizeof(ire::ShellF) + (size_t)K * sizeof(ire::DustF) +
-           (size_t)2 * K * sizeof(float) + (size_t)b->n_t * sizeof(float) + (size_t)b->n_t * K * sizeof(float) +
-           ire::guide_bytes(b->n_t) + ire::agg_lds_bytes(ire::trace_block_fp32());
+    return ire::batch_lds_bytes(b->max_table, (int)b->nu.size(), b->n_t);
 }
 
 // Build all tables, the per-model records and the ordered work items; upload.

@@ -53,6 +53,31 @@ struct ShellD { double r2_in, r2_out, rho, inv_rho; };
 struct DustF { float kA, kS, inv_kA, inv_kS, g, alb, kext, pad; };
 struct DustD { double kA, kS, inv_kA, inv_kS, g, alb, kext, pad; };
 
+// Byte offsets of the regions of an FP32 tracer's LDS.  Every region starts on
+// a 16-byte boundary: the tables before the escaping spectrum and the grouping
+// scratch hold 4-byte and 1-byte entries in counts that need not be even,
+// while those two regions hold doubles updated by LDS atomics, which must be
+// 8-byte aligned.  The shell table begins with kPadBelow pad records.  `sed`
+// and `rk` (the escaping spectrum and the k_A(rho) records) are absent from
+// the batched launch.
+struct LdsLayout { size_t sh, dust, cdf, G, D, guide, sed, rk, agg, total; };
+__host__ __device__ inline size_t lds_align16(size_t x) { return (x + 15) & ~(size_t)15; }
+__host__ __device__ inline LdsLayout lds_layout(int n_table, int K, int n_t, bool sed, bool rk, int block) {
+    LdsLayout L{};
+    size_t o = 0;
+    L.sh = o;    o = lds_align16(o + (size_t)(n_table + kPadBelow) * sizeof(ShellF));
+    L.dust = o;  o = lds_align16(o + (size_t)K * sizeof(DustF));
+    L.cdf = o;   o = lds_align16(o + (size_t)2 * K * sizeof(float));
+    L.G = o;     o = lds_align16(o + (size_t)n_t * sizeof(float));
+    L.D = o;     o = lds_align16(o + (size_t)n_t * K * sizeof(float));
+    L.guide = o; o = lds_align16(o + guide_bytes(n_t));
+    L.sed = o;   o = lds_align16(o + (sed ? (size_t)4 * K * sizeof(double) : 0));
+    L.rk = o;    o = lds_align16(o + (rk ? (size_t)(n_table + kPadBelow) * 2 * sizeof(float) : 0));
+    L.agg = o;   o = lds_align16(o + agg_lds_bytes(block));
+    L.total = o;
+    return L;
+}
+
 enum Counter {
     C_LAUNCH, C_CROSS, C_SCAT, C_ABS, C_ESCAPE, C_DIRECT, C_LIMIT, C_FLOOR,
     C_REEMIT_ABOVE, C_BELOW, C_ABOVE, C_PASS, C_SLOTS, C_COUNT
@@ -166,6 +191,7 @@ struct BatchFinalizeParams {
 };
 
 size_t trace_lds_bytes(int n_table, int K, int n_t);  // n_table = cavity + n + kSentinels
+size_t batch_lds_bytes(int max_table, int K, int n_t);
 size_t sed_lds_bytes(int K);
 hipError_t launch_trace(const TraceParams &p, int fp64, int aggregate, int grid, int block,
                         size_t lds, hipStream_t s);

@@ -31,9 +31,10 @@
 // b mod R and reads its slices as R times that copy's running total.
 //
 // Random numbers: Philox4x32-10 (Salmon et al. 2011), key = seed, counter =
-// (block, package id lo, package id hi, source); one block per event, a second
-// one for an absorption only when its slice reaches across a bin edge of the
-// G table or the re-emission radius is redrawn.  u = (x + 0.5) 2^-32.
+// (block, package id lo, package id hi, source); one block per event and a
+// second one for an absorption, which the FP32 kernels draw only when its slice
+// reaches across a bin edge of the G table or the re-emission radius is
+// redrawn.  u = (x + 0.5) 2^-32.
 //
 // Two instantiations: float stepping with all tables in LDS, and double
 // everywhere with tables read from global memory.  Absorbed-energy
@@ -726,8 +727,14 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
             // re-emission: a* uniform in the package's slice [A_before, A_before + E] / M
             // selects the G(T) bin whose difference spectrum is drawn.  A slice almost
             // never reaches across a bin edge (it is ~1e-6 of the shell's total), and
-            // then the bin does not depend on a*: its uniform is drawn only for a slice
-            // that does, so the first Philox block usually covers all five draws
+            // then the bin does not depend on a*.  The FP32 kernels use that: a* is
+            // drawn only for a slice that does reach across, so the first Philox block
+            // usually covers all five draws (a* or tau_S, frequency, direction,
+            // tau_A).  The FP64 kernels take the plain layout of two blocks per
+            // absorption, (a*, frequency, direction, tau_A) and (tau_S, re-emission
+            // radius), whether or not a* changes the bin: the same draws and the
+            // same distribution, one more block.
+            constexpr bool kTwoBlocks = std::is_same<R, double>::value;
             int row = 0;
             bool straddle = false;
             if (absorbing) {
@@ -736,7 +743,7 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
                 straddle = row < n_t && G[row] <= ahi;
                 lc.abs++;
             }
-            if ((absorbing && straddle) || (absorbing && o.reemit_uniform))
+            if (absorbing && (kTwoBlocks || straddle || o.reemit_uniform))
                 r2b = philox(blk++, pid_lo, pid_hi, (uint32_t)src, key0, key1);
             if (absorbing) {
                 if (straddle) {
@@ -809,7 +816,7 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
             // both free paths are redrawn after every event (Eq. 1), from
             // k e^{-k tau} when scaled (Eq. 8)
             R tauA = P<R>::nlog(P<R>::uni(absorbing ? r1.w : r1.z)) * inv_kA;
-            R tauS = P<R>::nlog(P<R>::uni(absorbing ? (straddle ? r2b.x : r1.x) : r1.w)) * inv_kS;
+            R tauS = P<R>::nlog(P<R>::uni(absorbing ? ((kTwoBlocks || straddle) ? r2b.x : r1.x) : r1.w)) * inv_kS;
             bool kw_new = kscale;
 
             // launch geometry and launch weights (Eqs. 2-3, Eq. 5, Eqs. 9-12)
@@ -1086,12 +1093,13 @@ template <int AGG, int WT>
 __global__ __launch_bounds__(kBlockFP32) void ire_trace_f32(TraceParams p) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int nsh = p.n + p.cavity + kSentinels, K = p.K, n_t = p.n_t;
-    ShellF *s_sh = reinterpret_cast<ShellF *>(smem) + kPadBelow;
-    DustF *s_dust = reinterpret_cast<DustF *>(s_sh + nsh);
-    float *s_cdf = reinterpret_cast<float *>(s_dust + K);
-    float *s_G = s_cdf + 2 * K;
-    float *s_D = s_G + n_t;
-    uint32_t *s_guide = reinterpret_cast<uint32_t *>(s_D + (size_t)n_t * K);
+    const LdsLayout L = lds_layout(nsh, K, n_t, true, true, kBlockFP32);
+    ShellF *s_sh = reinterpret_cast<ShellF *>(smem + L.sh) + kPadBelow;
+    DustF *s_dust = reinterpret_cast<DustF *>(smem + L.dust);
+    float *s_cdf = reinterpret_cast<float *>(smem + L.cdf);
+    float *s_G = reinterpret_cast<float *>(smem + L.G);
+    float *s_D = reinterpret_cast<float *>(smem + L.D);
+    uint32_t *s_guide = reinterpret_cast<uint32_t *>(smem + L.guide);
     for (int j = threadIdx.x - kPadBelow; j < nsh; j += blockDim.x) s_sh[j] = j < 0 ? ShellF{0, 0, 0, 0} : p.shf[j];
     for (int j = threadIdx.x; j < K; j += blockDim.x) s_dust[j] = p.dustf[j];
     for (int j = threadIdx.x; j < 2 * K; j += blockDim.x) s_cdf[j] = p.cdff[j];
@@ -1100,12 +1108,12 @@ __global__ __launch_bounds__(kBlockFP32) void ire_trace_f32(TraceParams p) {
     for (int j = threadIdx.x; j < nd; j += blockDim.x) s_D[j] = p.Df[j];
     const int ng = (int)(guide_bytes(n_t) / 4);
     for (int j = threadIdx.x; j < ng; j += blockDim.x) s_guide[j] = reinterpret_cast<const uint32_t *>(p.guide)[j];
-    double *s_sed = reinterpret_cast<double *>(s_guide + ng);
+    double *s_sed = reinterpret_cast<double *>(smem + L.sed);
     for (int j = threadIdx.x; j < 4 * K; j += blockDim.x) s_sed[j] = 0.0;
-    float2 *s_rk = reinterpret_cast<float2 *>(s_sed + 4 * K) + kPadBelow;
+    float2 *s_rk = reinterpret_cast<float2 *>(smem + L.rk) + kPadBelow;
     if constexpr (WT == 2)
         for (int j = threadIdx.x - kPadBelow; j < nsh; j += blockDim.x) s_rk[j] = j < 0 ? float2{0, 0} : p.rkf[j];
-    AggScratch *s_agg = reinterpret_cast<AggScratch *>(s_rk + nsh);
+    AggScratch *s_agg = reinterpret_cast<AggScratch *>(smem + L.agg);
     if constexpr (AGG == 2) wg_scratch_init(reinterpret_cast<WgScratch *>(s_agg));
     __syncthreads();
     ModelCtx<float> mc;
@@ -1196,13 +1204,14 @@ __global__ __launch_bounds__(kBlockFP32) void ire_trace_batch(BatchParams p) {
     __shared__ unsigned long long s_item;
     __shared__ unsigned long long s_cursor;
     const int K = p.K, n_t = p.n_t;
-    ShellF *s_sh = reinterpret_cast<ShellF *>(smem) + kPadBelow;
-    DustF *s_dust = reinterpret_cast<DustF *>(s_sh + p.max_table);
+    const LdsLayout L = lds_layout(p.max_table, K, n_t, false, false, kBlockFP32);
+    ShellF *s_sh = reinterpret_cast<ShellF *>(smem + L.sh) + kPadBelow;
+    DustF *s_dust = reinterpret_cast<DustF *>(smem + L.dust);
     if (threadIdx.x == 0) s_sh[-1] = ShellF{0, 0, 0, 0};
-    float *s_cdf = reinterpret_cast<float *>(s_dust + K);
-    float *s_G = s_cdf + 2 * K;
-    float *s_D = s_G + n_t;
-    uint32_t *s_guide = reinterpret_cast<uint32_t *>(s_D + (size_t)n_t * K);
+    float *s_cdf = reinterpret_cast<float *>(smem + L.cdf);
+    float *s_G = reinterpret_cast<float *>(smem + L.G);
+    float *s_D = reinterpret_cast<float *>(smem + L.D);
+    uint32_t *s_guide = reinterpret_cast<uint32_t *>(smem + L.guide);
     for (int j = threadIdx.x; j < K; j += blockDim.x) s_dust[j] = p.dustf[j];
     for (int j = threadIdx.x; j < 2 * K; j += blockDim.x) s_cdf[j] = p.cdff[j];
     for (int j = threadIdx.x; j < n_t; j += blockDim.x) s_G[j] = p.Gf[j];
@@ -1210,7 +1219,7 @@ __global__ __launch_bounds__(kBlockFP32) void ire_trace_batch(BatchParams p) {
     for (int j = threadIdx.x; j < nd; j += blockDim.x) s_D[j] = p.Df[j];
     const int ng = (int)(guide_bytes(n_t) / 4);
     for (int j = threadIdx.x; j < ng; j += blockDim.x) s_guide[j] = reinterpret_cast<const uint32_t *>(p.guide)[j];
-    AggScratch *s_agg = reinterpret_cast<AggScratch *>((reinterpret_cast<uintptr_t>(s_guide + ng) + 7) & ~(uintptr_t)7);
+    AggScratch *s_agg = reinterpret_cast<AggScratch *>(smem + L.agg);
 
     MethodOpts o;
     o.k_bg = p.k_bg;
@@ -1299,10 +1308,11 @@ __global__ void ire_finalize_batch(BatchFinalizeParams p) {
 }  // namespace
 
 size_t trace_lds_bytes(int n_table, int K, int n_t) {
-    return (size_t)(n_table + kPadBelow) * sizeof(ShellF) + (size_t)K * sizeof(DustF) +
-           (size_t)2 * K * sizeof(float) + (size_t)n_t * sizeof(float) + (size_t)n_t * K * sizeof(float) +
-           guide_bytes(n_t) + sed_lds_bytes(K) + (size_t)(n_table + kPadBelow) * sizeof(float2) +
-           agg_lds_bytes(kBlockFP32);
+    return lds_layout(n_table, K, n_t, true, true, kBlockFP32).total;
+}
+
+size_t batch_lds_bytes(int max_table, int K, int n_t) {
+    return lds_layout(max_table, K, n_t, false, false, kBlockFP32).total;
 }
 
 size_t sed_lds_bytes(int K) { return (size_t)4 * K * sizeof(double); }

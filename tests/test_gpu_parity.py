@@ -20,6 +20,7 @@ import pytest
 import mc_stats
 import oracle
 from paper_2408_13807_amd import workloads as wl
+from test_oracle_floor_clamp import clamp_model, floor_model
 
 pytestmark = pytest.mark.gpu
 
@@ -75,16 +76,35 @@ SERIAL_CASES = [
                                        albedo=np.full(8, 0.4)),
      dict(n_ps=2000), dict(k_A_rho=1, k_A_lowest=0.6, k_A_highest=2.0)),
     ("ext50_kArho_ffi", wl.cfg_external_small, dict(n_ext=1500), dict(k_A_rho=1, ffi=1)),
+    # the weight floor (Sect. 2.2.1): HG(g_E) re-emission weights 0.5/HG(mu') fall
+    # below w_floor = 0.5 for a known share of cosines; with one event per
+    # package, and with k_bg = 0.2 launch weights and no event limit
+    ("floor_gray_gE_limit1", floor_model, dict(n_ext=3000), dict(use_g_E=1, g_E=0.5, w_floor=0.5, max_events=1)),
+    ("floor_gray_kbg_gE", floor_model, dict(n_ext=2000), dict(k_bg=0.2, use_g_E=1, g_E=0.5, w_floor=0.5)),
+    # re-emission above the last table point (reading R7): a single shell heated
+    # past t_max = 5 K of an 8-point table, and the central cloud with t_max = 40 K
+    ("clamp_central_1shell", clamp_model, dict(n_ps=2000), {}),
+    ("central200_tmax40", lambda: dict(wl.cfg_central(), t_max=40.0), dict(n_ps=1000), {}),
 ]
+
+# counters that must be nonzero in a case, so that its branch is compared on real events
+FIRES = {"floor_gray_gE_limit1": ("n_floor", "n_limit"), "floor_gray_kbg_gE": ("n_floor",),
+         "clamp_central_1shell": ("n_reemit_above", "n_above"),
+         "central200_tmax40": ("n_reemit_above", "n_above")}
 
 
 @pytest.mark.parametrize("name,factory,npk,opts", SERIAL_CASES, ids=[c[0] for c in SERIAL_CASES])
 def test_serial_fp64_matches_oracle_elementwise(ire, name, factory, npk, opts):
     m = factory()
     print(f"case {name} {npk} {opts}", flush=True)
-    g = ire.run_model(m, seed=11, stepping=ire.IRE_FP64, max_lanes=1, **npk, **opts)
+    g = ire.run_model(m, seed=11, stepping=ire.IRE_FP64, max_lanes=1, allow_limit=True, **npk, **opts)
     o = oracle.run(m, seed=11, sed=True, **npk, **opts)
     assert counts(g["stats"]) == {k: o["stats"][k] for k in counts(g["stats"])}
+    assert g["stats"]["n_above"] == o["stats"]["n_above"] and g["stats"]["n_below"] == o["stats"]["n_below"]
+    for c in FIRES.get(name, ()):
+        assert o["stats"][c] > 0, (name, c)
+    if not o["stats"]["n_limit"]:
+        assert g["rc"] == ire.IRE_OK
     np.testing.assert_allclose(g["A"], o["A"], rtol=1e-9, atol=0)
     np.testing.assert_allclose(g["T"], o["T"], rtol=1e-9)
     # escaping spectrum per source and frequency, and its unscattered part
@@ -144,6 +164,25 @@ def test_parallel_weighted_against_oracle_ensemble(ire, opts):
     ok, f = mc_stats.compare_runs(r["T"], e["T"], e["A"], name=f"ext50 {opts}")
     print(f"ext50 weighted {opts}: {f * 100:.1f}% of shells within max(1%, 3 sigma)")
     assert ok
+
+
+@pytest.mark.parametrize("n_t,K", [(511, 64), (101, 8), (3, 7)])
+def test_parallel_fp32_odd_table_sizes(ire, n_t, K):
+    # odd temperature grids and frequency counts: the FP32 tracers' LDS regions
+    # after the 4-byte tables (escaping spectrum, grouping scratch) hold doubles
+    # updated by LDS atomics and must stay 8-byte aligned
+    if K == 64:
+        m = dict(wl.cfg_external_small(), n_t=n_t)
+    else:
+        m = dict(wl.external_sphere(n=20, tau_V=2.0, K=K), n_t=n_t)
+    e = oracle.ensemble(m, n_ext=100_000, seeds=range(1, 17))
+    for agg in (1, 2):
+        r = ire.run_model(m, n_ext=100_000, seed=108, aggregate=agg)
+        ok, f = mc_stats.compare_runs(r["T"], e["T"], e["A"], name=f"n_t={n_t} K={K} aggregate={agg}")
+        print(f"n_t={n_t} K={K} aggregate={agg}: {f * 100:.1f}% of shells within max(1%, 3 sigma)")
+        assert ok
+        sd = r["sed"].sum()
+        assert abs(sd / sum(r["stats"]["escaped"]) - 1) < 1e-9
 
 
 @pytest.mark.parametrize("name,factory,npk,gold,opts", [
