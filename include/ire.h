@@ -195,6 +195,27 @@ int ire_get_sed(ire_model *m, double *sed, double *sed_direct);
  * memory on hip_stream (kept alive by the caller until the work completes). */
 int ire_get_results_dev(ire_model *m, double *absorbed_dev, double *T_dev, void *hip_stream);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc.  Equivalent to
+ * ire_run(m, n_ext, n_ps, seed) followed by ire_get_results_dev(absorbed_dev,
+ * T_dev): a complete run of the handle's current model and options from zero
+ * absorbed energy, asynchronous on hip_stream, writing absorbed[n] (erg/s) and
+ * T[n] (K) into caller device memory (kept alive by the caller until the work
+ * completes).  It calls no hipMalloc, hipFree or other allocating routine: the
+ * run's accumulators, event counters, tallies, package cursor and escaping
+ * spectrum live in a fixed array inside the library, one per GPU (about 520 KB,
+ * held until the process ends), cleared by a fill kernel at the start of every
+ * call.  Limits: shells x accumulator groups (options.replicas) <= 4096 and
+ * K <= 255 (IRE_E_INVALID beyond).  The model's tables must already be on the
+ * device: call ire_run or ire_begin once after the last setter (IRE_E_STATE
+ * otherwise).  The handle's own run, statistics and results are not touched;
+ * event counts of this call are not returned.  Every call on one GPU shares
+ * that GPU's array, so calls that overlap on one GPU (on different streams,
+ * from different threads, or with different handles) race and must be
+ * serialised by the caller. */
+int ire_run_noalloc(ire_model *m, uint64_t n_ext, uint64_t n_ps, uint64_t seed, double *absorbed_dev,
+                    double *T_dev, void *hip_stream);
+
 /* Human-readable description of the last failure on m (owned by m). */
 const char *ire_last_error(const ire_model *m);
 

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -153,6 +154,130 @@ int check_ready(ire_model *m) {
     return IRE_OK;
 }
 
+// Shape and parameters of one trace launch of the handle's current model and
+// options (everything but the package energies, ids, seed and the accumulator,
+// counter and spectrum buffers, which the caller fills in).
+struct TraceLaunch {
+    ire::TraceParams p{};
+    int fp64 = 0, agg = 0, grid = 1, block = 64;
+    size_t lds = 0;
+};
+
+int trace_launch_setup(ire_model *m, int replicas, uint64_t n_ext, uint64_t n_ps, TraceLaunch &L) {
+    // schedule: with one running total per shell, per-lane or per-wave atomics on the few addresses bound
+    // the launch, and grouping the absorptions of the whole workgroup (its waves pass together, at 52 parked
+    // lanes, or once 6 waves are there) makes the fewest; with accumulator groups the launch is
+    // instruction-bound, and per-wave grouping at 40 parked lanes is the better balance
+    const int agg = m->opt.aggregate >= 0 ? m->opt.aggregate : (replicas > 1 ? 1 : 2);
+    if (agg == 2 && m->rho.size() >= (1u << 22))
+        return m->fail(IRE_E_INVALID, "aggregate = 2 supports fewer than 2^22 shells");
+    hipError_t e;
+    const int n = (int)m->rho.size(), K = (int)m->nu.size();
+    const int fp64 = m->opt.stepping == IRE_FP64;
+    // packages per lane: one for FP64 and for runs with a cap on packages in flight
+    size_t lds = 0;
+    int block, grid;
+    if (fp64) {
+        block = 256;
+        grid = m->n_cu * 8;
+    } else {
+        lds = ire::trace_lds_bytes(n + (m->r_edges[0] > 0.0 ? 1 : 0) + ire::kSentinels, K, m->n_t);
+        if (lds > m->max_lds)
+            return m->fail(IRE_E_INVALID, "FP32 tables need %zu bytes of LDS, the device has %zu; use IRE_FP64",
+                           lds, m->max_lds);
+        if ((e = ire::trace_configure(0, agg, lds)) != hipSuccess) return m->hip_fail(e, "configure tracer");
+        block = ire::trace_block_fp32();
+        grid = m->n_cu;
+    }
+    if (m->opt.max_lanes > 0) {
+        const int waves = (m->opt.max_lanes + 63) / 64;
+        const int wpb = block / 64;
+        grid = std::min(grid, (waves + wpb - 1) / wpb);
+        if (grid < 1) grid = 1;
+    }
+    ire::TraceParams &p = L.p;
+    p = ire::TraceParams{};
+    p.n = n; p.K = K; p.n_t = m->n_t;
+    p.cavity = m->r_edges[0] > 0.0 ? 1 : 0;
+    p.shf = m->shf.p; p.dustf = m->dustf.p; p.cdff = m->cdff.p; p.Gf = m->Gf.p; p.Df = m->Df.p;
+    p.shd = m->shd.p; p.dustd = m->dustd.p; p.cdfd = m->cdfd.p; p.Gd = m->Gd.p; p.Dd = m->Dd.p;
+    p.invM = m->invM.p;
+    p.guide = m->guide.p;
+    p.g_lg0 = m->g_lg0;
+    p.g_scale = m->g_scale;
+    p.n_ext = n_ext; p.n_ps = n_ps;
+    p.k_bg = m->opt.k_bg; p.ffi = m->opt.ffi; p.reemit_uniform = m->opt.reemit_uniform;
+    p.w_floor = m->opt.w_floor; p.max_events = m->opt.max_events; p.max_lanes = m->opt.max_lanes;
+    p.use_g_E = m->opt.use_g_E; p.g_E = m->opt.g_E; p.use_g_S = m->opt.use_g_S; p.g_S = m->opt.g_S;
+    p.k_A = m->opt.k_A; p.k_S = m->opt.k_S;
+    p.k_A_rho = m->opt.k_A_rho; p.rkf = m->rkf.p; p.rkd = m->rkd.p;
+    p.replicas = replicas;
+    {
+        const unsigned long long waves = (unsigned long long)grid * (block / 64);
+        unsigned long long c = (n_ext + n_ps) / (waves * 8ull);
+        p.chunk = std::min<unsigned long long>(std::max<unsigned long long>(c, 64ull), 4096ull);
+    }
+    p.batch = m->opt.batch > 0 ? m->opt.batch : (agg == 2 ? 52 : (replicas > 1 ? 40 : 64));
+    p.quorum = m->opt.quorum > 0 ? m->opt.quorum : 6;
+    L.fp64 = fp64;
+    L.agg = agg;
+    L.grid = grid;
+    L.block = block;
+    L.lds = lds;
+    return IRE_OK;
+}
+
+// ---- the scratch of ire_run_noalloc: a fixed device array per GPU holding the
+// run's event counters, tallies and package cursor, its escaping spectrum and
+// its absorbed-energy accumulators, so that the call allocates nothing.
+constexpr int kNoAllocShellCopies = 4096;    // shells x accumulator groups
+constexpr int kNoAllocMaxK = 255;            // frequencies (the guide tables' limit too)
+constexpr size_t kScratchStatsBytes = 256;
+constexpr size_t kScratchSedBytes = 8192;    // >= 4 * kNoAllocMaxK doubles
+constexpr size_t kScratchBytes =
+    kScratchStatsBytes + kScratchSedBytes + (size_t)kNoAllocShellCopies * ire::kAccStride * sizeof(double);
+static_assert(sizeof(ire::DevStats) <= kScratchStatsBytes, "scratch counters");
+static_assert(4 * kNoAllocMaxK * sizeof(double) <= kScratchSedBytes, "scratch spectrum");
+
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};   // the array's device address on each GPU (HIP_SYMBOL is host-side only)
+
+// Resolve the array's address on `device`, which must be current.  Once per
+// device; later calls return the kept address.
+hipError_t resolve_scratch(int device, void **out) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_dev[device] = ptr;
+    }
+    *out = g_scratch_dev[device];
+    return hipSuccess;
+}
+
+struct NoAllocScratch {
+    ire::DevStats *stats = nullptr;
+    double *sed = nullptr;
+    double *A = nullptr;
+};
+
+int noalloc_scratch(ire_model *m, NoAllocScratch &sc) {
+    void *base = nullptr;
+    const hipError_t e = resolve_scratch(m->device, &base);
+    if (e != hipSuccess) return m->hip_fail(e, "scratch address");
+    unsigned char *b = static_cast<unsigned char *>(base);
+    sc.stats = reinterpret_cast<ire::DevStats *>(b);
+    sc.sed = reinterpret_cast<double *>(b + kScratchStatsBytes);
+    sc.A = reinterpret_cast<double *>(b + kScratchStatsBytes + kScratchSedBytes);
+    return IRE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -204,6 +329,13 @@ int ire_create(int hip_device, ire_model **out) {
     }
     m->max_lds = (size_t)lds;
     if (hipEventCreate(&m->ev0) != hipSuccess || hipEventCreate(&m->ev1) != hipSuccess) {
+        delete m;
+        return IRE_E_DEVICE;
+    }
+    // the no-allocation entry point's scratch address on this device, resolved
+    // here with the device current (once per device)
+    void *scratch_ptr = nullptr;
+    if (resolve_scratch(hip_device, &scratch_ptr) != hipSuccess) {
         delete m;
         return IRE_E_DEVICE;
     }
@@ -381,75 +513,77 @@ int ire_advance(ire_model *m, uint64_t n_ext, uint64_t n_ps, void *hip_stream) {
     if (n_ext + n_ps == 0) return IRE_OK;
     if (m->replicas > 1 && m->opt.max_lanes > 0)
         return m->fail(IRE_E_STATE, "a run begun with replicas > 1 cannot continue with max_lanes > 0");
-    // schedule: with one running total per shell, per-lane or per-wave atomics on the few addresses bound
-    // the launch, and grouping the absorptions of the whole workgroup (its waves pass together, at 52 parked
-    // lanes, or once 6 waves are there) makes the fewest; with accumulator groups the launch is
-    // instruction-bound, and per-wave grouping at 40 parked lanes is the better balance
-    const int agg = m->opt.aggregate >= 0 ? m->opt.aggregate : (m->replicas > 1 ? 1 : 2);
-    if (agg == 2 && m->rho.size() >= (1u << 22))
-        return m->fail(IRE_E_INVALID, "aggregate = 2 supports fewer than 2^22 shells");
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
     hipError_t e;
     if ((e = hipSetDevice(m->device)) != hipSuccess) return m->hip_fail(e, "hipSetDevice");
-    const int n = (int)m->rho.size(), K = (int)m->nu.size();
-    const int fp64 = m->opt.stepping == IRE_FP64;
-    // packages per lane: one for FP64 and for runs with a cap on packages in flight
-    size_t lds = 0;
-    int block, grid;
-    if (fp64) {
-        block = 256;
-        grid = m->n_cu * 8;
-    } else {
-        lds = ire::trace_lds_bytes(n + (m->r_edges[0] > 0.0 ? 1 : 0) + ire::kSentinels, K, m->n_t);
-        if (lds > m->max_lds)
-            return m->fail(IRE_E_INVALID, "FP32 tables need %zu bytes of LDS, the device has %zu; use IRE_FP64",
-                           lds, m->max_lds);
-        if ((e = ire::trace_configure(0, agg, lds)) != hipSuccess) return m->hip_fail(e, "configure tracer");
-        block = ire::trace_block_fp32();
-        grid = m->n_cu;
-    }
-    if (m->opt.max_lanes > 0) {
-        const int waves = (m->opt.max_lanes + 63) / 64;
-        const int wpb = block / 64;
-        grid = std::min(grid, (waves + wpb - 1) / wpb);
-        if (grid < 1) grid = 1;
-    }
-    ire::TraceParams p{};
-    p.n = n; p.K = K; p.n_t = m->n_t;
-    p.cavity = m->r_edges[0] > 0.0 ? 1 : 0;
-    p.shf = m->shf.p; p.dustf = m->dustf.p; p.cdff = m->cdff.p; p.Gf = m->Gf.p; p.Df = m->Df.p;
-    p.shd = m->shd.p; p.dustd = m->dustd.p; p.cdfd = m->cdfd.p; p.Gd = m->Gd.p; p.Dd = m->Dd.p;
-    p.invM = m->invM.p;
-    p.guide = m->guide.p;
-    p.g_lg0 = m->g_lg0;
-    p.g_scale = m->g_scale;
+    TraceLaunch L;
+    int rc = trace_launch_setup(m, m->replicas, n_ext, n_ps, L);
+    if (rc) return rc;
+    ire::TraceParams &p = L.p;
     p.eps[0] = m->eps[0]; p.eps[1] = m->eps[1];
-    p.n_ext = n_ext; p.n_ps = n_ps;
     p.pid0[0] = m->n_done[0]; p.pid0[1] = m->n_done[1];
     p.seed = m->seed;
-    p.k_bg = m->opt.k_bg; p.ffi = m->opt.ffi; p.reemit_uniform = m->opt.reemit_uniform;
-    p.w_floor = m->opt.w_floor; p.max_events = m->opt.max_events; p.max_lanes = m->opt.max_lanes;
-    p.use_g_E = m->opt.use_g_E; p.g_E = m->opt.g_E; p.use_g_S = m->opt.use_g_S; p.g_S = m->opt.g_S;
-    p.k_A = m->opt.k_A; p.k_S = m->opt.k_S;
-    p.k_A_rho = m->opt.k_A_rho; p.rkf = m->rkf.p; p.rkd = m->rkd.p;
     p.A = m->A.p; p.stats = m->stats.p; p.sed = m->sed.p;
-    p.replicas = m->replicas;
-    {
-        const unsigned long long waves = (unsigned long long)grid * (block / 64);
-        unsigned long long c = (n_ext + n_ps) / (waves * 8ull);
-        p.chunk = std::min<unsigned long long>(std::max<unsigned long long>(c, 64ull), 4096ull);
-    }
-    p.batch = m->opt.batch > 0 ? m->opt.batch : (agg == 2 ? 52 : (m->replicas > 1 ? 40 : 64));
-    p.quorum = m->opt.quorum > 0 ? m->opt.quorum : 6;
-    if ((e = ire::launch_zero(nullptr, n, m->stats.p, 0, nullptr, 0, s)) != hipSuccess) return m->hip_fail(e, "cursor reset");
+    if ((e = ire::launch_zero(nullptr, 0, m->stats.p, 0, nullptr, 0, s)) != hipSuccess) return m->hip_fail(e, "cursor reset");
     if ((e = hipEventRecord(m->ev0, s)) != hipSuccess) return m->hip_fail(e, "event");
-    if ((e = ire::launch_trace(p, fp64, agg, grid, block, lds, s)) != hipSuccess)
+    if ((e = ire::launch_trace(p, L.fp64, L.agg, L.grid, L.block, L.lds, s)) != hipSuccess)
         return m->hip_fail(e, "trace launch");
     if ((e = hipEventRecord(m->ev1, s)) != hipSuccess) return m->hip_fail(e, "event");
     m->timed = true;
     m->last_stream = s;
     m->n_done[0] += n_ext;
     m->n_done[1] += n_ps;
+    return IRE_OK;
+}
+
+int ire_run_noalloc(ire_model *m, uint64_t n_ext, uint64_t n_ps, uint64_t seed, double *absorbed_dev,
+                    double *T_dev, void *hip_stream) {
+    if (!m) return IRE_E_INVALID;
+    int rc = check_ready(m);
+    if (rc) return rc;
+    if (m->dirty)
+        return m->fail(IRE_E_STATE, "the model's tables are not on the device: call ire_run (or ire_begin) after "
+                                    "the last setter before ire_run_noalloc");
+    if (n_ext > 0 && m->J.empty()) return m->fail(IRE_E_STATE, "external packages requested but no external field is set");
+    if (n_ps > 0 && m->S.empty()) return m->fail(IRE_E_STATE, "point-source packages requested but no point source is set");
+    if (n_ext > 0 && !(m->L_ext > 0.0)) return m->fail(IRE_E_STATE, "the external field carries no power on this grid");
+    const int n = (int)m->rho.size(), K = (int)m->nu.size();
+    if (n > 0 && (!absorbed_dev || !T_dev)) return m->fail(IRE_E_INVALID, "null output");
+    const int R = m->opt.replicas;
+    if ((long long)n * R > kNoAllocShellCopies)
+        return m->fail(IRE_E_INVALID, "ire_run_noalloc holds at most %d shells x accumulator groups, not %d x %d",
+                       kNoAllocShellCopies, n, R);
+    if (K > kNoAllocMaxK) return m->fail(IRE_E_INVALID, "ire_run_noalloc holds at most %d frequencies", kNoAllocMaxK);
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    hipError_t e;
+    if ((e = hipSetDevice(m->device)) != hipSuccess) return m->hip_fail(e, "hipSetDevice");
+    NoAllocScratch sc;
+    if ((rc = noalloc_scratch(m, sc)) != IRE_OK) return rc;
+    // the scratch keeps the last call's contents: clear the accumulators, counters,
+    // tallies, cursor and escaping spectrum with a fill kernel
+    if ((e = ire::launch_zero(sc.A, R * n, sc.stats, 1, sc.sed, 4 * K, s)) != hipSuccess)
+        return m->hip_fail(e, "clear scratch");
+    if (n_ext + n_ps > 0) {
+        TraceLaunch L;
+        if ((rc = trace_launch_setup(m, R, n_ext, n_ps, L)) != IRE_OK) return rc;
+        ire::TraceParams &p = L.p;
+        p.eps[0] = n_ext ? m->L_ext / (double)n_ext : 0.0;
+        p.eps[1] = n_ps ? m->L_ps / (double)n_ps : 0.0;
+        p.pid0[0] = 0; p.pid0[1] = 0;
+        p.seed = seed;
+        p.A = sc.A; p.stats = sc.stats; p.sed = sc.sed;
+        if ((e = ire::launch_trace(p, L.fp64, L.agg, L.grid, L.block, L.lds, s)) != hipSuccess)
+            return m->hip_fail(e, "trace launch");
+    }
+    ire::FinalizeParams f{};
+    f.n = n;
+    f.n_t = m->n_t;
+    f.A = sc.A; f.invM = m->invM.p; f.Gd = m->Gd.p; f.lnG = m->lnGd.p; f.lnT = m->lnTd.p;
+    f.replicas = R;
+    f.t_min = m->t_min; f.t_max = m->t_max;
+    f.A_out = absorbed_dev; f.T_out = T_dev;
+    f.stats = sc.stats;
+    if ((e = ire::launch_finalize(f, s)) != hipSuccess) return m->hip_fail(e, "finalize launch");
     return IRE_OK;
 }
 

@@ -26,7 +26,8 @@ IRE_FP64 = 1
 EXPORTS = ("ire_default_options", "ire_create", "ire_destroy", "ire_set_shells", "ire_set_dust",
            "ire_set_temperature_grid", "ire_set_external_field", "ire_set_point_source",
            "ire_set_options", "ire_run", "ire_begin", "ire_advance", "ire_reset", "ire_tune_schedule", "ire_sync",
-           "ire_get_results", "ire_get_stats", "ire_get_results_dev", "ire_get_sed", "ire_last_error", "ire_planck",
+           "ire_get_results", "ire_get_stats", "ire_get_results_dev", "ire_get_sed", "ire_run_noalloc",
+           "ire_last_error", "ire_planck",
            "ire_batch_default_options", "ire_batch_create", "ire_batch_destroy", "ire_batch_set_dust",
            "ire_batch_set_temperature_grid", "ire_batch_set_sources", "ire_batch_set_models",
            "ire_batch_set_options", "ire_batch_run", "ire_batch_get", "ire_batch_autotune",
@@ -119,6 +120,7 @@ _lib.ire_sync.argtypes = [_H]
 _lib.ire_get_results.argtypes = [_H, _DP, _DP, ct.POINTER(Stats)]
 _lib.ire_get_stats.argtypes = [_H, ct.POINTER(Stats)]
 _lib.ire_get_results_dev.argtypes = [_H, ct.c_void_p, ct.c_void_p, ct.c_void_p]
+_lib.ire_run_noalloc.argtypes = [_H, ct.c_uint64, ct.c_uint64, ct.c_uint64, ct.c_void_p, ct.c_void_p, ct.c_void_p]
 _lib.ire_get_sed.argtypes = [_H, _DP, _DP]
 _lib.ire_last_error.argtypes = [_H]
 _lib.ire_last_error.restype = ct.c_char_p
@@ -290,6 +292,11 @@ class IREModel:
 
     def results_dev(self, absorbed_ptr: int | None, T_ptr: int | None, stream=None):
         self._check(_lib.ire_get_results_dev(self._h, absorbed_ptr, T_ptr, _stream_ptr(stream)))
+
+    def run_noalloc(self, n_ext: int, n_ps: int, seed: int, absorbed_ptr: int, T_ptr: int, stream=None):
+        """ire_run_noalloc: a whole run into caller device memory, with no device allocation."""
+        self._check(_lib.ire_run_noalloc(self._h, int(n_ext), int(n_ps), int(seed), absorbed_ptr, T_ptr,
+                                         _stream_ptr(stream)))
 
 
 def run_model(model: dict, n_ext: int = 0, n_ps: int = 0, seed: int = 1, device: int = 0,
