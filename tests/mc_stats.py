@@ -61,3 +61,17 @@ def compare_runs(T, T_runs, A_runs, **kw) -> tuple[bool, float]:
     A_runs = np.asarray(A_runs, np.float64)
     return compare(T, T_runs.mean(0), T_runs.std(0, ddof=1), A_runs.mean(0), A_runs.std(0, ddof=1),
                    len(T_runs), **kw)
+
+
+def zero_deposit_failures(A, A_ref_mean, eps, p_max: float = 1e-6) -> list[int]:
+    """Shells that took no deposit in the run (A = 0, so T sits at the table's
+    floor) although the reference runs make that improbable.  In an unweighted
+    run every deposit is one package energy eps, so a shell's deposit count is
+    A / eps, close to Poisson with mean lam = <A_ref> / eps, and P(no deposit) =
+    exp(-lam).  A shell fails when exp(-lam) < p_max.  (A check that every
+    shell with all reference runs above the floor must be above it too would
+    fail by chance where lam is a few deposits: with lam = 3 a run misses the
+    shell 5 % of the time.)"""
+    A = np.asarray(A, np.float64)
+    lam = np.asarray(A_ref_mean, np.float64) / eps
+    return [int(i) for i in np.nonzero((A == 0.0) & (np.exp(-lam) < p_max))[0]]

@@ -56,6 +56,67 @@ def test_batch_matches_single_model_ensembles(ire, params):
     b.close()
 
 
+def study_sample(params):
+    """16 study models over the whole range: tau_V up to ~1000, 300-400 shells,
+    both source types; the last four cheap enough for the oracle."""
+    n, tau, cen = params["n"], params["tau_V"], params["central"]
+    big = n >= 300
+    sel = []
+
+    def take(mask, k):
+        sel.extend([int(i) for i in np.nonzero(mask)[0] if int(i) not in sel][:k])
+
+    take(big & (tau > 300) & (cen == 1), 3)
+    take(big & (tau > 300) & (cen == 0), 3)
+    take(tau > 800, 2)
+    take((tau > 3) & (tau < 300) & (cen == 1), 2)
+    take((tau > 3) & (tau < 300) & (cen == 0), 2)
+    take(big & (tau < 3) & (cen == 1), 2)
+    take(big & (tau < 3) & (cen == 0), 2)
+    return sel
+
+
+def test_batch_split_models_over_the_study_range(ire, params):
+    # every model traced as five work items (4 x 65536 packages and a ragged
+    # rest) of one persistent launch, against 16 single-model runs of the same
+    # model and budget and, for the optically thin ones, 16 oracle runs
+    models = study_sample(params)
+    assert len(models) == 16 and max(params["tau_V"][models]) > 900
+    assert sum(300 <= params["n"][m] <= 400 for m in models) >= 10
+    N = 300_000
+    p2 = {k: v.copy() for k, v in params.items()}
+    p2["n_pkg"][models] = N
+    b = ire.batch_from_workloads(p2, models)
+    b.set_options(item_packages=65536)
+    b.run()
+    r = b.results()
+    s = r["stats"]
+    assert s["n_models"] == 16 and s["n_items"] == 16 * 5 and s["n_launch"] == 16 * N
+    assert abs((s["escaped"] + s["ffi_escaped"] + s["terminated"]) / s["L_total"] - 1) < 1e-9
+    Ts, As = split(b, r["T"]), split(b, r["A"])
+    for j, m in enumerate(models):
+        mm = wl.batch_model(params, m)
+        key = "n_ps" if params["central"][m] else "n_ext"
+        print(f"model {m}: {params['n'][m]} shells, tau_V {params['tau_V'][m]:.1f}, {key}", flush=True)
+        runs = [ire.run_model(mm, seed=200 + k, **{key: N}) for k in range(16)]
+        eps = (runs[0]["stats"]["L_ext"] + runs[0]["stats"]["L_ps"]) / N
+        A_ref = np.mean([x["A"] for x in runs], axis=0)
+        ok, f = mc_stats.compare_runs(Ts[j], [x["T"] for x in runs], [x["A"] for x in runs], name=f"model {m}")
+        print(f"  vs single-model runs: {f * 100:.1f}% of shells within max(1%, 3 sigma)")
+        assert ok, (m, f)
+        assert mc_stats.zero_deposit_failures(As[j], A_ref, eps) == [], m
+        # the batched model's absorbed power against the single-model runs' spread
+        tot = np.array([x["A"].sum() for x in runs])
+        assert abs(As[j].sum() - tot.mean()) <= max(4 * tot.std(ddof=1), 1e-3 * tot.mean()), m
+        if j >= 12:
+            e = oracle.ensemble(mm, seeds=range(1, 17), **{key: N})
+            ok, f = mc_stats.compare_runs(Ts[j], e["T"], e["A"], name=f"model {m} oracle")
+            print(f"  vs oracle: {f * 100:.1f}% of shells within max(1%, 3 sigma)")
+            assert ok, (m, f)
+            assert mc_stats.zero_deposit_failures(As[j], e["A"].mean(axis=0), eps) == [], m
+    b.close()
+
+
 def test_batch_matches_oracle(ire, params):
     models = pick(params, 4, tau_max=3.0, seed=2)
     scale = 0.01

@@ -50,3 +50,17 @@ def test_pooled_sigma_uses_neighbours():
     std = np.array([1, 1, 1, 1, 0.01, 1, 1, 1, 1.0])
     s = mc_stats.pooled_sigma(mean, std)
     assert s[4] == 1.0 and np.all(s >= std)
+
+
+def test_zero_deposit_check():
+    rng = np.random.default_rng(3)
+    eps = 2.5
+    lam = np.array([0.5, 3.0, 8.0, 20.0, 200.0])
+    # runs drawn from the reference distribution: misses only where exp(-lam) is not tiny
+    for _ in range(200):
+        A = rng.poisson(lam) * eps
+        assert mc_stats.zero_deposit_failures(A, lam * eps, eps) == []
+    # a well-hit shell left at zero fails
+    A = rng.poisson(lam) * eps
+    A[3] = 0.0
+    assert mc_stats.zero_deposit_failures(A, lam * eps, eps) == [3]
