@@ -248,16 +248,41 @@ def predict_with_fallback(net: SurNet, params: dict, models, threshold: float = 
 
 def model_errors(T: np.ndarray, T_ref: np.ndarray, row_off: np.ndarray, stat: str = "median") -> np.ndarray:
     """Per-model relative temperature error |T - T_ref| / T_ref over the shells
-    of each model: the median over shells (default; robust to the few shells
-    whose reference is itself Monte Carlo noise) or the mean."""
+    of each model: "max" (the worst shell), "p95" (95th percentile over the
+    shells), "median" or "mean".  The reference is itself a Monte Carlo run, so
+    its own noise in rarely hit shells enters every statistic, most the max."""
     d = np.abs(T - T_ref) / T_ref
     n = np.diff(row_off)
     out = np.zeros(len(n))
+    nz = n > 0
     if stat == "mean":
-        nz = n > 0
         out[nz] = np.add.reduceat(d, row_off[:-1][nz]) / n[nz]
         return out
-    for j in range(len(n)):
-        if n[j]:
-            out[j] = np.median(d[row_off[j]:row_off[j + 1]])
+    if stat == "max":
+        out[nz] = np.maximum.reduceat(d, row_off[:-1][nz])
+        return out
+    q = {"median": 0.5, "p95": 0.95}[stat]
+    for j in np.nonzero(nz)[0]:
+        out[j] = np.quantile(d[row_off[j]:row_off[j + 1]], q)
+    return out
+
+
+def error_summary(T_sur: np.ndarray, T_ire: np.ndarray, T_ref: np.ndarray, row_off: np.ndarray,
+                  accepted: np.ndarray, limit: float = 0.02) -> dict:
+    """Fractions of models within `limit` of the reference by each per-model
+    statistic, for the surrogate on the models it accepts, for every model
+    after the fallback (accepted: surrogate, others: IRE), and for IRE alone."""
+    out = {}
+    for stat in ("max", "p95", "median"):
+        e_s = model_errors(T_sur, T_ref, row_off, stat)
+        e_i = model_errors(T_ire, T_ref, row_off, stat)
+        e_f = np.where(accepted, e_s, e_i)
+        out[stat] = dict(
+            surrogate_all=float(np.mean(e_s <= limit)),
+            surrogate_accepted=float(np.mean(e_s[accepted] <= limit)) if accepted.any() else None,
+            after_fallback=float(np.mean(e_f <= limit)),
+            ire_alone=float(np.mean(e_i <= limit)),
+            median_error_surrogate_accepted=float(np.median(e_s[accepted])) if accepted.any() else None,
+            median_error_after_fallback=float(np.median(e_f)),
+            median_error_ire_alone=float(np.median(e_i)))
     return out
