@@ -177,38 +177,170 @@ struct ModelInputs {
     }
 };
 
+// Inference kernel.  One workgroup (4 waves) per tile of kR = 128 rows; the
+// activations of the tile live in ONE LDS buffer that every hidden layer
+// overwrites in place (the layer's products are complete in registers before
+// the buffer is rewritten), so a workgroup takes ~80 KB of LDS and two run on
+// a CU.  Wave w computes output features [64w, 64w + 64) of every layer:
+// accumulators start at the bias, the weight fragments of the next kAhead k
+// steps are in flight in a register ring and the activation fragments of the
+// next step are requested before the current step's eight MFMAs; SiLU costs
+// one exp2 and one reciprocal, and pairs of results are converted to BF16
+// together.  The output layer w_out . h is folded into the last hidden
+// layer's epilogue: each lane sums its 32 features of 4 rows, the two
+// half-waves and then the 4 waves are added, and the thread of each row
+// accumulates the moments of T over the members.
+constexpr int kPredictWaves = kThreads / 64;
+
+__device__ __forceinline__ float silu_fast(float z) {
+    // z / (1 + e^-z) with the hardware exp2 and reciprocal
+    return z * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.44269504088896341f * z));
+}
+
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    const bf16x2 v = __builtin_convertvector(f32x2{a, b}, bf16x2);
+    return __builtin_bit_cast(uint32_t, v);
+}
+
+__device__ __forceinline__ float bf16_lo(uint32_t u) { return __builtin_bit_cast(float, u << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t u) { return __builtin_bit_cast(float, u & 0xFFFF0000u); }
+
+// acc[a][b] = bias + W . hin^T for this wave's 64 output features and the kR
+// rows; lane l holds in entry r of acc[a][b] feature 64 w + 32 a + 8 (r >> 2)
+// + 4 (l >> 5) + (r & 3) of row 32 b + (l & 31).
+template <int K>
+__device__ __forceinline__ void predict_layer(const __bf16 *W, const float *bias, const __bf16 *hin, int ldin,
+                                              f32x16 (&acc)[2][4]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int half = lane >> 5, l32 = lane & 31;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const float *bb = bias + wave * 64 + a * 32 + 4 * half;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const float4 bv = *reinterpret_cast<const float4 *>(bb + 8 * g);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                acc[a][b][4 * g + 0] = bv.x;
+                acc[a][b][4 * g + 1] = bv.y;
+                acc[a][b][4 * g + 2] = bv.z;
+                acc[a][b][4 * g + 3] = bv.w;
+            }
+        }
+    }
+    const __bf16 *wrow0 = W + (size_t)(wave * 64 + l32) * K + 8 * half;
+    const __bf16 *wrow1 = wrow0 + (size_t)32 * K;
+    const __bf16 *hrow = hin + l32 * ldin + 8 * half;
+    constexpr int kSteps = K / 16;
+    constexpr int kAhead = kSteps < 4 ? kSteps : 4;
+    bf16x8 wa[kAhead][2], hb[2][4];
+#pragma unroll
+    for (int s = 0; s < kAhead; ++s) {
+        wa[s][0] = *reinterpret_cast<const bf16x8 *>(wrow0 + 16 * s);
+        wa[s][1] = *reinterpret_cast<const bf16x8 *>(wrow1 + 16 * s);
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) hb[0][b] = *reinterpret_cast<const bf16x8 *>(hrow + b * 32 * ldin);
+#pragma unroll
+    for (int st = 0; st < kSteps; ++st) {
+        const int k = 16 * st;
+        const bf16x8 c0 = wa[st % kAhead][0], c1 = wa[st % kAhead][1];
+        if (st + kAhead < kSteps) {
+            wa[st % kAhead][0] = *reinterpret_cast<const bf16x8 *>(wrow0 + k + 16 * kAhead);
+            wa[st % kAhead][1] = *reinterpret_cast<const bf16x8 *>(wrow1 + k + 16 * kAhead);
+        }
+        if (st + 1 < kSteps) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                hb[(st + 1) & 1][b] = *reinterpret_cast<const bf16x8 *>(hrow + b * 32 * ldin + k + 16);
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            acc[0][b] = mfma(c0, hb[st & 1][b], acc[0][b]);
+            acc[1][b] = mfma(c1, hb[st & 1][b], acc[1][b]);
+        }
+    }
+}
+
+// Epilogue of a hidden layer: SiLU of the accumulators, rounded to BF16.
+// Hidden layers store the values into the tile buffer; the last hidden layer
+// instead folds the output layer in: this wave's part of w_out . h for the 4
+// rows b * 32 + l32, summed over the two half-waves into ysum[wave][row].
+__device__ __forceinline__ void predict_epilogue(const f32x16 (&acc)[2][4], __bf16 *hout, bool last,
+                                                 const float *wout, float *ysum) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int half = lane >> 5, l32 = lane & 31;
+    float y[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int o = wave * 64 + a * 32 + 8 * g + 4 * half;
+            float4 w = float4{0.0f, 0.0f, 0.0f, 0.0f};
+            if (last) w = *reinterpret_cast<const float4 *>(wout + o);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const uint32_t lo = pack_bf16x2(silu_fast(acc[a][b][4 * g]), silu_fast(acc[a][b][4 * g + 1]));
+                const uint32_t hi = pack_bf16x2(silu_fast(acc[a][b][4 * g + 2]), silu_fast(acc[a][b][4 * g + 3]));
+                if (last)
+                    y[b] += w.x * bf16_lo(lo) + w.y * bf16_hi(lo) + w.z * bf16_lo(hi) + w.w * bf16_hi(hi);
+                else
+                    *reinterpret_cast<uint2 *>(hout + (b * 32 + l32) * kLd + o) = uint2{lo, hi};
+                // keep the scheduler from gathering every transcendental of the tile at once
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    if (last) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            y[b] += __shfl_xor(y[b], 32, 64);
+            if (half == 0) ysum[wave * kR + b * 32 + l32] = y[b];
+        }
+    }
+}
+
 template <typename Inputs>
-__global__ __launch_bounds__(kThreads) void sur_predict_kernel(NetView v, Inputs in, int64_t n, float *mean_logT,
-                                                               float *spread) {
+__global__ __launch_bounds__(kThreads, 2) void sur_predict_kernel(NetView v, Inputs in, int64_t n, float *mean_logT,
+                                                                  float *spread) {
     extern __shared__ __align__(16) unsigned char smem[];
     __bf16 *xs = reinterpret_cast<__bf16 *>(smem);
-    __bf16 *h0 = xs + kR * kLdX;
-    __bf16 *h1 = h0 + kR * kLd;
+    __bf16 *h = xs + kR * kLdX;
+    float *ysum = reinterpret_cast<float *>(h + kR * kLd);
     const int64_t row0 = (int64_t)blockIdx.x * kR;
     in(n, row0, v, xs);
     float s_log = 0.0f, s_T = 0.0f, s_T2 = 0.0f;
+    f32x16 acc[2][4];
     for (int m = 0; m < v.members; ++m) {
         const __bf16 *W = v.W + (size_t)m * v.w_stride;
         const float *b = v.b + (size_t)m * v.b_stride;
-        __syncthreads();
-        layer_fwd<false>(W, b, kIn, xs, kLdX, h0, nullptr, nullptr, row0, n);
-        __bf16 *hin = h0, *hout = h1;
-        for (int l = 1; l < v.depth; ++l) {
-            __syncthreads();
-            layer_fwd<false>(W + (size_t)kW * kIn + (size_t)(l - 1) * kW * kW, b + l * kW, kW, hin, kLd, hout,
-                             nullptr, nullptr, row0, n);
-            __bf16 *t = hin; hin = hout; hout = t;
+        __syncthreads();                    // inputs staged / the previous member's sums read
+        for (int l = 0; l < v.depth; ++l) {
+            if (l == 0) {
+                predict_layer<kIn>(W, b, xs, kLdX, acc);
+            } else {
+                __syncthreads();            // every wave's features of layer l - 1 stored
+                predict_layer<kW>(W + (size_t)kW * kIn + (size_t)(l - 1) * kW * kW, b + l * kW, h, kLd, acc);
+                if (l + 1 < v.depth) __syncthreads();   // every wave has read layer l - 1: overwrite in place
+            }
+            // (layer 0 reads the input tile, and the previous member's last layer only read h)
+            predict_epilogue(acc, h, l + 1 == v.depth, v.wout + (size_t)m * kW, ysum);
         }
-        __syncthreads();
-        const float y = out_row(hin, v.wout + (size_t)m * kW, v.bout[m]);
-        const float lt = y * v.y_std + v.y_mean;       // log10 T of this member
-        const float T = exp10f(lt);
-        s_log += lt;
-        s_T += T;
-        s_T2 += T * T;
+        __syncthreads();                    // the waves' output sums
+        if (threadIdx.x < kR) {
+            float y = v.bout[m];
+#pragma unroll
+            for (int w = 0; w < kPredictWaves; ++w) y += ysum[w * kR + threadIdx.x];
+            const float lt = y * v.y_std + v.y_mean;       // log10 T of this member
+            const float T = exp10f(lt);
+            s_log += lt;
+            s_T += T;
+            s_T2 += T * T;
+        }
     }
-    if ((threadIdx.x & 1) == 0) {
-        const int64_t row = row0 + (threadIdx.x >> 1);
+    if (threadIdx.x < kR) {
+        const int64_t row = row0 + threadIdx.x;
         if (row < n) {
             const float M = (float)v.members;
             const float mT = s_T / M;
@@ -509,7 +641,8 @@ __global__ void sur_step_inc(unsigned long long *step) {
 
 }  // namespace
 
-size_t predict_lds() { return (size_t)kR * kLdX * 2 + (size_t)2 * kR * kLd * 2; }
+size_t predict_lds() { return (size_t)kR * kLdX * 2 + (size_t)kR * kLd * 2 + (size_t)kPredictWaves * kR * sizeof(float); }
+size_t train_fwd_lds() { return (size_t)kR * kLdX * 2 + (size_t)2 * kR * kLd * 2; }
 size_t bwd_lds() { return (size_t)2 * kR * kLd * 2; }
 size_t wgrad_lds() { return (size_t)(kW + 128) * (kR + 8) * 2; }
 
@@ -522,7 +655,7 @@ hipError_t configure() {
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)predict_lds())) != hipSuccess)
         return e;
     if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(&sur_train_fwd),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)predict_lds())) != hipSuccess)
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)train_fwd_lds())) != hipSuccess)
         return e;
     if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(&sur_train_bwd),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bwd_lds())) != hipSuccess)
@@ -561,7 +694,7 @@ hipError_t launch_train_step(const NetView &v, const TrainView &t, const float *
     const unsigned groups = (unsigned)((t.batch + (int64_t)kR * kWgChunks - 1) / ((int64_t)kR * kWgChunks));
     if (gather) hipLaunchKernelGGL(sur_gather, dim3(256), dim3(256), 0, s, X, y, n_data, t, step, seed, M);
     hipLaunchKernelGGL(sur_zero, dim3(1), dim3(64), 0, s, t.loss, (size_t)M);
-    hipLaunchKernelGGL(sur_train_fwd, dim3(blocks, M), dim3(kThreads), predict_lds(), s, v, t);
+    hipLaunchKernelGGL(sur_train_fwd, dim3(blocks, M), dim3(kThreads), train_fwd_lds(), s, v, t);
     hipLaunchKernelGGL(sur_train_bwd, dim3(blocks, M), dim3(kThreads), bwd_lds(), s, v, t);
     hipLaunchKernelGGL(sur_train_wgrad, dim3(groups, M * v.depth), dim3(kThreads), wgrad_lds(), s, v, t);
     hipLaunchKernelGGL(sur_train_outgrad, dim3((unsigned)((t.batch + 255) / 256), M), dim3(kW), 0, s, v, t);
