@@ -259,6 +259,9 @@ typedef struct ire_batch_options {
     int32_t use_g_S;
     double g_S;
     double k_A, k_S;
+    int32_t k_A_rho;          /* Sect. 3.2: absorption scaling by density per model, as ire_options
+                                 (each model's scale runs over its own shells' densities) */
+    double k_A_lowest, k_A_highest;
 } ire_batch_options;
 
 typedef struct ire_batch_stats {

@@ -26,6 +26,10 @@ def hipcc() -> str:
     return os.path.join(rocm, "bin", "hipcc")
 
 
+# the vector-ALU issue-rate tool behind the tracer's roofline peak (profiling only)
+VALU_RATE = os.path.join(LIB_DIR, "valu_rate")
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(LIB_DIR, exist_ok=True)
     tmp = LIB + ".tmp"
@@ -35,6 +39,12 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    tool = [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
+            "-packed-fp32-ops", os.path.join(CSRC, "valu_rate.hip"), "-o", VALU_RATE + ".tmp"]
+    if verbose:
+        print(" ".join(tool), flush=True)
+    subprocess.check_call(tool)
+    os.replace(VALU_RATE + ".tmp", VALU_RATE)
     return LIB
 
 

@@ -43,6 +43,7 @@ struct ire_batch {
     double L_total = 0.0;
     // device
     DevBuf<ire::ShellF> shells;
+    DevBuf<float2> rkf;               // k_A(rho) records, laid out as `shells` (only with k_A_rho)
     DevBuf<ire::DustF> dustf;
     DevBuf<float> cdff, Gf, Df;
     DevBuf<unsigned char> guide;
@@ -82,7 +83,7 @@ struct ire_batch {
 namespace {
 
 size_t lds_bytes(const ire_batch *b) {
-    return ire::batch_lds_bytes(b->max_table, (int)b->nu.size(), b->n_t);
+    return ire::batch_lds_bytes(b->max_table, (int)b->nu.size(), b->n_t, b->opt.k_A_rho != 0);
 }
 
 // Build all tables, the per-model records and the ordered work items; upload.
@@ -111,6 +112,7 @@ int prepare(ire_batch *b) {
         while (kmed[s] < K - 1 && cdf[s * K + kmed[s]] < 0.5) kmed[s]++;
 
     std::vector<ire::ShellF> shf;
+    std::vector<float2> rkf;
     std::vector<ire::ShellD> shd;
     std::vector<double> invM;
     b->mdev.clear();
@@ -131,6 +133,13 @@ int prepare(ire_batch *b) {
         dm.src = md.source;
         dm.acc_off = (int)d_off;
         ire::host::build_shell_table(re, rh, n, shf, shd, invM);
+        if (b->opt.k_A_rho) {
+            // the model's absorption scaling over its own shells' densities, at its shell_off
+            std::vector<float2> mf;
+            std::vector<double2> md;
+            ire::host::build_absorption_scaling(re, rh, n, b->opt.k_A_lowest, b->opt.k_A_highest, mf, md);
+            rkf.insert(rkf.end(), mf.begin(), mf.end());
+        }
         const double R = re[n];
         const double L = md.source == IRE_SRC_EXTERNAL ? 4.0 * kPi * R * R * kPi * sumJ * md.scale : md.scale;
         dm.eps = L / (double)md.n_packages;
@@ -178,6 +187,8 @@ int prepare(ire_batch *b) {
     ire::host::build_guides(b->dt, cdf.data(), K, guide, b->g_lg0, b->g_scale);
     hipError_t he;
     if ((he = hipSetDevice(b->device)) != hipSuccess) return b->hip_fail(he, "hipSetDevice");
+    if (b->opt.k_A_rho && (he = b->rkf.upload(rkf)) != hipSuccess)
+        return he == hipErrorOutOfMemory ? b->fail(IRE_E_NOMEM, "device allocation failed") : b->hip_fail(he, "upload");
     if ((he = b->shells.upload(shf)) != hipSuccess || (he = b->dustf.upload(b->dt.df)) != hipSuccess ||
         (he = b->cdff.upload(cdff)) != hipSuccess || (he = b->Gf.upload(Gf)) != hipSuccess ||
         (he = b->Df.upload(Df)) != hipSuccess || (he = b->Gd.upload(b->dt.G)) != hipSuccess ||
@@ -224,6 +235,8 @@ int enqueue(ire_batch *b, hipStream_t s) {
     p.g_S = b->opt.g_S;
     p.k_A = b->opt.k_A;
     p.k_S = b->opt.k_S;
+    p.k_A_rho = b->opt.k_A_rho;
+    p.rkf = b->opt.k_A_rho ? b->rkf.p : nullptr;
     p.stats = b->stats.p;
     const size_t lds = lds_bytes(b);
     hipError_t e;
@@ -344,6 +357,9 @@ int ire_batch_default_options(ire_batch_options *o) {
     o->g_S = 0.0;
     o->k_A = 1.0;
     o->k_S = 1.0;
+    o->k_A_rho = 0;
+    o->k_A_lowest = 3.0;
+    o->k_A_highest = 1.0;
     return IRE_OK;
 }
 
@@ -474,9 +490,16 @@ int ire_batch_set_options(ire_batch *b, const ire_batch_options *o) {
     if (o->aggregate != 0 && o->aggregate != 1) return b->fail(IRE_E_INVALID, "aggregate must be 0 or 1");
     if (o->batch < 0 || o->batch > 64) return b->fail(IRE_E_INVALID, "batch must be in [0, 64]");
     if (o->use_graph != 0 && o->use_graph != 1) return b->fail(IRE_E_INVALID, "use_graph must be 0 or 1");
-    const bool items_change = o->item_packages != b->opt.item_packages;
+    if (o->k_A_rho != 0 && o->k_A_rho != 1) return b->fail(IRE_E_INVALID, "k_A_rho must be 0 or 1");
+    if (o->k_A_rho && (o->k_A != 1.0 || !(o->k_A_lowest > 0.0) || !(o->k_A_highest > 0.0) ||
+                       !std::isfinite(o->k_A_lowest) || !std::isfinite(o->k_A_highest)))
+        return b->fail(IRE_E_INVALID, "k_A_rho needs k_A = 1 and finite k_A_lowest, k_A_highest > 0");
+    // item sizes and the k_A(rho) records are built with the tables
+    const bool tables_change = o->item_packages != b->opt.item_packages || o->k_A_rho != b->opt.k_A_rho ||
+                               (o->k_A_rho && (o->k_A_lowest != b->opt.k_A_lowest ||
+                                               o->k_A_highest != b->opt.k_A_highest));
     b->opt = *o;
-    if (items_change) b->dirty = true;
+    if (tables_change) b->dirty = true;
     b->drop_graph();
     return IRE_OK;
 }

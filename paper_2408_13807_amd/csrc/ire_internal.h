@@ -179,6 +179,8 @@ struct BatchParams {
     unsigned long long max_events;
     int use_g_E, use_g_S;             // weighted sampling (Table 1)
     double g_E, g_S, k_A, k_S;
+    int k_A_rho;                      // absorption scaling by density: per-shell {k rho, 1/(k rho)} below
+    const float2 *rkf;                // laid out as `shells` (each model's table at its shell_off)
     DevStats *stats;                  // stats->cursor counts taken items
 };
 
@@ -191,7 +193,7 @@ struct BatchFinalizeParams {
 };
 
 size_t trace_lds_bytes(int n_table, int K, int n_t);  // n_table = cavity + n + kSentinels
-size_t batch_lds_bytes(int max_table, int K, int n_t);
+size_t batch_lds_bytes(int max_table, int K, int n_t, bool k_A_rho);
 size_t sed_lds_bytes(int K);
 hipError_t launch_trace(const TraceParams &p, int fp64, int aggregate, int grid, int block,
                         size_t lds, hipStream_t s);

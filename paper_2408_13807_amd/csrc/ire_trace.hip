@@ -1204,10 +1204,12 @@ __global__ __launch_bounds__(kBlockFP32) void ire_trace_batch(BatchParams p) {
     __shared__ unsigned long long s_item;
     __shared__ unsigned long long s_cursor;
     const int K = p.K, n_t = p.n_t;
-    const LdsLayout L = lds_layout(p.max_table, K, n_t, false, false, kBlockFP32);
+    const LdsLayout L = lds_layout(p.max_table, K, n_t, false, WT == 2, kBlockFP32);
     ShellF *s_sh = reinterpret_cast<ShellF *>(smem + L.sh) + kPadBelow;
     DustF *s_dust = reinterpret_cast<DustF *>(smem + L.dust);
     if (threadIdx.x == 0) s_sh[-1] = ShellF{0, 0, 0, 0};
+    float2 *s_rk = WT == 2 ? reinterpret_cast<float2 *>(smem + L.rk) + kPadBelow : nullptr;
+    if (WT == 2 && threadIdx.x == 0) s_rk[-1] = float2{0, 0};
     float *s_cdf = reinterpret_cast<float *>(smem + L.cdf);
     float *s_G = reinterpret_cast<float *>(smem + L.G);
     float *s_D = reinterpret_cast<float *>(smem + L.D);
@@ -1249,6 +1251,8 @@ __global__ __launch_bounds__(kBlockFP32) void ire_trace_batch(BatchParams p) {
         const BatchModelDev bm = p.models[item.model];
         const int nt = bm.n + bm.cav + kSentinels;
         for (int j = threadIdx.x; j < nt; j += blockDim.x) s_sh[j] = p.shells[bm.shell_off + j];
+        if constexpr (WT == 2)
+            for (int j = threadIdx.x; j < nt; j += blockDim.x) s_rk[j] = p.rkf[bm.shell_off + j];
         __syncthreads();
         ModelCtx<float> mc;
         mc.sh = s_sh;
@@ -1265,7 +1269,7 @@ __global__ __launch_bounds__(kBlockFP32) void ire_trace_batch(BatchParams p) {
         mc.pid0[1] = item.first;
         mc.seed = bm.seed;
         trace_model<float, AGG, WT>(mc, o, s_dust, s_cdf, s_G, s_D, K, n_t,
-                                    reinterpret_cast<const unsigned char *>(s_guide), p.g_lg0, p.g_scale, nullptr,
+                                    reinterpret_cast<const unsigned char *>(s_guide), p.g_lg0, p.g_scale, s_rk,
                                     &s_cursor,
                                      64ull, false, lc, nullptr, s_agg + threadIdx.x / kWave, nullptr);
     }
@@ -1311,8 +1315,8 @@ size_t trace_lds_bytes(int n_table, int K, int n_t) {
     return lds_layout(n_table, K, n_t, true, true, kBlockFP32).total;
 }
 
-size_t batch_lds_bytes(int max_table, int K, int n_t) {
-    return lds_layout(max_table, K, n_t, false, false, kBlockFP32).total;
+size_t batch_lds_bytes(int max_table, int K, int n_t, bool k_A_rho) {
+    return lds_layout(max_table, K, n_t, false, k_A_rho, kBlockFP32).total;
 }
 
 size_t sed_lds_bytes(int K) { return (size_t)4 * K * sizeof(double); }
@@ -1332,7 +1336,9 @@ static const void *f32_kernel(int aggregate, int wt) {
 
 // the batched launch groups by wave (aggregate 2 is a single-model schedule)
 static const void *batch_kernel(int aggregate, int wt) {
-    if (wt >= 1) return aggregate ? reinterpret_cast<const void *>(&ire_trace_batch<1, 1>)
+    if (wt == 2) return aggregate ? reinterpret_cast<const void *>(&ire_trace_batch<1, 2>)
+                                  : reinterpret_cast<const void *>(&ire_trace_batch<0, 2>);
+    if (wt == 1) return aggregate ? reinterpret_cast<const void *>(&ire_trace_batch<1, 1>)
                                   : reinterpret_cast<const void *>(&ire_trace_batch<0, 1>);
     return aggregate ? reinterpret_cast<const void *>(&ire_trace_batch<1, 0>)
                      : reinterpret_cast<const void *>(&ire_trace_batch<0, 0>);
@@ -1359,6 +1365,7 @@ static int weighting(const TraceParams &p) {
 }
 
 static int weighting(const BatchParams &p) {
+    if (p.k_A_rho) return 2;
     return (p.use_g_E || p.use_g_S || p.k_A != 1.0 || p.k_S != 1.0 || p.ffi == 2) ? 1 : 0;
 }
 
@@ -1403,9 +1410,12 @@ hipError_t launch_finalize(const FinalizeParams &p, hipStream_t s) {
 int trace_block_fp32() { return kBlockFP32; }
 
 hipError_t batch_configure(int aggregate, size_t lds) {
-    hipError_t e = hipFuncSetAttribute(batch_kernel(aggregate, 0), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(batch_kernel(aggregate, 1), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    for (int wt = 0; wt < 3; ++wt) {
+        const hipError_t e = hipFuncSetAttribute(batch_kernel(aggregate, wt), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_trace_batch(const BatchParams &p, int aggregate, int grid, size_t lds, hipStream_t s) {

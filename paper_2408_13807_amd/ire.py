@@ -69,7 +69,8 @@ class BatchOptions(ct.Structure):
                 ("max_events", ct.c_uint64), ("reemit_uniform", ct.c_int32), ("aggregate", ct.c_int32),
                 ("batch", ct.c_int32), ("item_packages", ct.c_uint64), ("use_graph", ct.c_int32),
                 ("use_g_E", ct.c_int32), ("g_E", ct.c_double), ("use_g_S", ct.c_int32), ("g_S", ct.c_double),
-                ("k_A", ct.c_double), ("k_S", ct.c_double)]
+                ("k_A", ct.c_double), ("k_S", ct.c_double), ("k_A_rho", ct.c_int32), ("k_A_lowest", ct.c_double),
+                ("k_A_highest", ct.c_double)]
 
 
 class BatchStats(ct.Structure):

@@ -15,6 +15,14 @@
     python -m paper_2408_13807_amd.profiling sur-predict [rows]
         surrogate ensemble prediction (5 members, 4 x 256) of `rows` (default
         2.1e7) device-resident rows, three launches: the MFMA kernel to profile
+    python -m paper_2408_13807_amd.profiling valu-rate
+        lane-operations per second of plain FP32 FMAs and adds, hardware
+        transcendentals and 32-bit high multiplies (csrc/valu_rate.hip): the
+        measured side of the VALU peak
+    python -m paper_2408_13807_amd.profiling sur-train [steps]
+        `steps` (default 200) training steps of the same ensemble on random
+        rows, 4096 per member and step: the forward, backward and weight-gradient
+        MFMA kernels to profile
 """
 from __future__ import annotations
 
@@ -134,9 +142,39 @@ def main(argv: list[str]) -> int:
             net.predict_dev(X.data_ptr(), n, mean.data_ptr(), spread.data_ptr())
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
-            flop = 2.0 * n * 5 * (32 * 256 + 3 * 256 * 256 + 256)
+            # dense FLOPs of the network's 7 inputs (the input tile is padded to 32 for the MFMA)
+            flop = 2.0 * n * 5 * (7 * 256 + 3 * 256 * 256 + 256)
             print(json.dumps({"rows": n, "s": dt, "rows_per_s": n / dt, "tflops": flop / dt / 1e12}), flush=True)
         net.close()
+    elif cmd == "sur-train":
+        # training steps of a 5-member ensemble on random rows (4096 rows per member and step)
+        import time
+        import torch
+        from paper_2408_13807_amd import surrogate
+        steps = int(argv[1]) if len(argv) > 1 else 200
+        rng = np.random.default_rng(0)
+        X = rng.normal(size=(1 << 20, 6)).astype(np.float32)
+        y = (1.3 + 0.3 * np.tanh(X[:, 0]) + 0.1 * X[:, 5]).astype(np.float32)
+        net = surrogate.SurNet(members=5, depth=4, seed=1)
+        net.set_normalization(np.zeros(6), np.ones(6), 1.3, 0.3)
+        net.train(X, y, steps=4, batch=4096)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss = net.train(X, y, steps=steps, batch=4096)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        # forward, backward and weight gradient: 3x the forward FLOPs of 5 x 4096 rows per step
+        flop = 3 * 2.0 * 4096 * 5 * (7 * 256 + 3 * 256 * 256 + 256) * steps
+        print(json.dumps({"steps": steps, "s": dt, "steps_per_s": steps / dt, "tflops": flop / dt / 1e12,
+                          "loss": [float(v) for v in loss]}), flush=True)
+        net.close()
+    elif cmd == "valu-rate":
+        import os
+        import subprocess
+        from paper_2408_13807_amd import build
+        if not os.path.exists(build.VALU_RATE):
+            raise SystemExit(f"{build.VALU_RATE} is not built; run __graft_entry__.build()")
+        print(subprocess.run([build.VALU_RATE], check=True, capture_output=True, text=True).stdout, end="")
     elif cmd == "copy":
         import torch
         n = (int(argv[1]) if len(argv) > 1 else 1024) << 18   # float32 elements

@@ -117,6 +117,42 @@ def test_batch_split_models_over_the_study_range(ire, params):
     b.close()
 
 
+def test_batch_density_dependent_kA(ire, params):
+    # Sect. 3.2: absorption scaling by density (k from 3 at each model's lowest
+    # density to 1 at its highest) in the batched launch, against single-model
+    # runs with the same option and, for optically thin models, the oracle
+    models = pick(params, 10, tau_max=30.0, seed=5)
+    N = 200_000
+    p2 = {k: v.copy() for k, v in params.items()}
+    p2["n_pkg"][models] = N
+    b = ire.batch_from_workloads(p2, models)
+    b.set_options(k_A_rho=1, item_packages=65536)
+    b.run()
+    r = b.results()
+    s = r["stats"]
+    assert s["n_models"] == 10 and s["n_launch"] == 10 * N
+    # weighted runs conserve energy in expectation: escaped + stopped power near the sources' total
+    assert abs((s["escaped"] + s["ffi_escaped"] + s["terminated"]) / s["L_total"] - 1) < 0.05
+    for j, (m, T) in enumerate(zip(models, split(b, r["T"]))):
+        mm = wl.batch_model(params, m)
+        key = "n_ps" if params["central"][m] else "n_ext"
+        runs = [ire.run_model(mm, seed=300 + k, k_A_rho=1, **{key: N}) for k in range(16)]
+        ok, f = mc_stats.compare_runs(T, [x["T"] for x in runs], [x["A"] for x in runs], name=f"model {m} k_A(rho)")
+        print(f"model {m} (tau_V {params['tau_V'][m]:.2f}, {params['n'][m]} shells): {f * 100:.1f}% of shells "
+              f"within max(1%, 3 sigma) of single-model k_A(rho) runs", flush=True)
+        assert ok, (m, f)
+        if params["tau_V"][m] < 1.0 and params["n"][m] < 150:
+            e = oracle.ensemble(mm, seeds=range(1, 17), k_A_rho=1, **{key: N})
+            ok, f = mc_stats.compare_runs(T, e["T"], e["A"], name=f"model {m} k_A(rho) oracle")
+            print(f"  vs oracle: {f * 100:.1f}%")
+            assert ok, (m, f)
+    # the option is rejected with a constant k_A
+    with pytest.raises(ire.IREError) as e:
+        b.set_options(k_A_rho=1, k_A=2.0)
+    assert e.value.code == ire.IRE_E_INVALID
+    b.close()
+
+
 def test_batch_matches_oracle(ire, params):
     models = pick(params, 4, tau_max=3.0, seed=2)
     scale = 0.01
