@@ -36,8 +36,14 @@ VALU_PER_EVENT = {"cross": 18.95, "launch": 277.61, "scat": 280.96, "abs": 309.2
 # the tracer as profiled and set to None whenever the kernel changes.
 TRAFFIC_BYTES = {"ext101_tauV10_1e8": 6.180e8}
 
-# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = VALU lane-instruction issue peak
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# MI355X VALU lane-instruction issue peak: the published FP32 vector rate of
+# 157.3 TFLOP/s is 78.6e12 FMAs per second, i.e. 256 CUs x 4 SIMDs x 32 lanes
+# at 2.4 GHz.  Plain (unpacked) FP32 instructions reach it: a stream of
+# independent v_fma_f32 / v_add_f32 measures 5.5-5.8e13 lane-operations per
+# second on the device (profiles/valu_issue_rate.md), above the 16-lane
+# figure of 3.9e13 an older reading of the peak used; the hardware
+# transcendentals run at a quarter of the plain rate.
+VALU_PEAK_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
 
 WORKLOADS = {
     # name: (factory, packages, description)
@@ -181,7 +187,7 @@ def bench_surrogate(args) -> dict:
     train_scale = float(env("IRE_SUR_TRAIN_SCALE", "1.0"))
     fit_steps = int(env("IRE_SUR_STEPS", "60000"))
     n_eval = int(env("IRE_SUR_EVAL_MODELS", "1024"))
-    ref_scale = float(env("IRE_SUR_REF_SCALE", "4.0"))
+    ref_scale = float(env("IRE_SUR_REF_SCALE", "16.0"))
     n_inf = int(env("IRE_SUR_MODELS", "1000000"))
     thr = float(env("IRE_SUR_THRESHOLD", "0.02"))
     torch.cuda.set_device(0)
@@ -208,22 +214,32 @@ def bench_surrogate(args) -> dict:
                 train_data_s=t1 - t0, fit_steps=fit_steps, fit_s=t2 - t1,
                 final_loss=[float(v) for v in net.last_loss])
 
-    # accuracy on held-out models against IRE at ref_scale x their budgets
+    # accuracy on held-out models: the surrogate and the tracer at 1x and 4x each
+    # model's budget against IRE at ref_scale x the budget (independent seeds)
     pe = wl.batch_parameters(n_eval, seed=202)
     ev = np.arange(n_eval)
+
+    def reseeded(k):
+        q = dict(pe)
+        q["seed"] = pe["seed"] + np.uint64(k << 20)
+        return q
+
     ref = S.ire_profiles(pe, ev, package_scale=ref_scale, progress=chunks("reference"))
-    own = S.ire_profiles(pe, ev, package_scale=1.0, progress=chunks("IRE at 1x"))
+    own = S.ire_profiles(reseeded(1), ev, package_scale=1.0, progress=chunks("IRE at 1x"))
+    own4 = S.ire_profiles(reseeded(2), ev, package_scale=4.0, progress=chunks("IRE at 4x"))
     p = S.predict_models(net, pe, ev)
     Ts = 10.0 ** p["logT"].astype(np.float64)
     acc = p["model_spread"] <= thr
-    summary = S.error_summary(Ts, own["T"], ref["T"], ref["row_off"], acc)
+    summary = S.error_summary(Ts, ref["T"], ref["row_off"], acc, {"ire_1x": own["T"], "ire_4x": own4["T"]})
     # the fallback gate at other spread thresholds: accepted share and models within 2 % (worst shell)
     gates = {}
     for g in (0.005, 0.01, 0.02, 0.03, 0.05):
         a = p["model_spread"] <= g
-        gs = S.error_summary(Ts, own["T"], ref["T"], ref["row_off"], a)["max"]
-        gates[f"{g:g}"] = {"accepted_fraction": float(a.mean()), "after_fallback_within_2pct_max": gs["after_fallback"],
-                           "accepted_within_2pct_max": gs["surrogate_accepted"]}
+        gs = S.error_summary(Ts, ref["T"], ref["row_off"], a, {"ire_1x": own["T"]})
+        gates[f"{g:g}"] = {"accepted_fraction": float(a.mean()),
+                           "after_fallback_within_2pct_max": gs["max"]["after_fallback"],
+                           "after_fallback_within_2pct_p95": gs["p95"]["after_fallback"],
+                           "accepted_within_2pct_max": gs["max"]["surrogate_accepted"]}
     note.update(eval_models=n_eval, eval_reference=f"IRE at {ref_scale:g}x each model's package budget",
                 error_definitions="per model, over its shells, of |T - T_ref| / T_ref: the worst shell (max), the 95th "
                                   "percentile (p95) and the median; fractions of models within 2 % by each",

@@ -72,6 +72,7 @@ struct sur_net {
     sur::TrainView tview(int64_t batch) const {
         sur::TrainView t{};
         t.batch = batch;
+        t.ld = (batch + 15) / 16 * 16;
         t.xb = xb.p;
         t.yb = yb.p;
         t.x16 = x16.p;
@@ -100,6 +101,7 @@ uint64_t splitmix(uint64_t &x) {
 
 int ensure_workspace(sur_net *s, int64_t batch) {
     if (batch <= s->cap_batch) return IRE_OK;
+    // batch is a multiple of 128 here, so it also covers the feature-major arrays' padded stride
     const size_t M = s->members, L = s->depth, B = (size_t)batch, W = sur::kWidth;
     hipError_t e;
     if ((e = s->xb.ensure(M * B * sur::kFeatures)) != hipSuccess || (e = s->yb.ensure(M * B)) != hipSuccess ||

@@ -42,11 +42,14 @@ struct ModelRows {
 
 struct TrainView {
     int64_t batch;              // rows per member and step
+    int64_t ld;                 // row stride of the feature-major arrays: batch rounded up to 16
     float *xb, *yb;             // [M][batch][kFeatures], [M][batch] gathered mini-batch
-    __bf16 *x16;                // [M][batch][kIn] normalised inputs
-    __bf16 *h;                  // [M][depth][batch][kWidth] activations
-    float *ds;                  // [M][depth][batch][kWidth] SiLU'(z)
-    __bf16 *delta;              // [M][depth][batch][kWidth] d loss / d z
+    // feature-major (rows contiguous per feature) so that the weight gradient
+    // reads its MFMA fragments straight from them; rows [batch, ld) hold zero deltas
+    __bf16 *x16;                // [M][kIn][ld] normalised inputs
+    __bf16 *h;                  // [M][depth][kWidth][ld] activations
+    float *ds;                  // [M][depth][batch][kWidth] SiLU'(z) (row-major)
+    __bf16 *delta;              // [M][depth][kWidth][ld] d loss / d z
     float *out, *g;             // [M][batch] outputs and d loss / d output
     float *loss;                // [M] mean squared error of the step (normalised target)
     float *grad, *master, *adam_m, *adam_v;  // [M][p_stride]

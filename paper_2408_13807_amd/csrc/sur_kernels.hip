@@ -64,7 +64,7 @@ __device__ __forceinline__ void load_inputs(const float *X, int64_t n, int64_t r
 // activation and SiLU'(z) are also stored to global memory (rows < n).
 template <bool TRAIN>
 __device__ __forceinline__ void layer_fwd(const __bf16 *W, const float *bias, int K, const __bf16 *hin, int ldin, __bf16 *hout,
-                          __bf16 *h_g, float *ds_g, int64_t row0, int64_t n) {
+                          __bf16 *h_g, float *ds_g, int64_t row0, int64_t n, int64_t ld) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int half = lane >> 5, l32 = lane & 31;
     f32x16 acc[2][4];
@@ -103,10 +103,13 @@ __device__ __forceinline__ void layer_fwd(const __bf16 *W, const float *bias, in
                     dv[q] = dsilu(z);
                 }
                 *reinterpret_cast<bf16x4 *>(hout + row * kLd + o) = hv;
-                if (TRAIN && row0 + row < n) {
-                    *reinterpret_cast<bf16x4 *>(h_g + (row0 + row) * kW + o) = hv;
-                    *reinterpret_cast<float4 *>(ds_g + (row0 + row) * kW + o) = float4{dv[0], dv[1], dv[2], dv[3]};
+                if (TRAIN && row0 + row < ld) {
+                    // feature-major activations (rows of 32 lanes contiguous per feature)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) h_g[(size_t)(o + q) * ld + row0 + row] = hv[q];
                 }
+                if (TRAIN && row0 + row < n)
+                    *reinterpret_cast<float4 *>(ds_g + (row0 + row) * kW + o) = float4{dv[0], dv[1], dv[2], dv[3]};
             }
         }
 }
@@ -381,20 +384,22 @@ __global__ __launch_bounds__(kThreads) void sur_train_fwd(NetView v, TrainView t
     const __bf16 *W = v.W + (size_t)m * v.w_stride;
     const float *b = v.b + (size_t)m * v.b_stride;
     const float *X = t.xb + (size_t)m * n * kFeatures;
+    const int64_t ld = t.ld;
     load_inputs(X, n, row0, v, xs);
-    // keep the normalised input tile for the first layer's weight gradient
-    for (int j = threadIdx.x; j < kR * kIn; j += blockDim.x) {
-        const int r = j / kIn, c = j % kIn;
-        if (row0 + r < n) t.x16[(size_t)m * n * kIn + (row0 + r) * kIn + c] = xs[r * kLdX + c];
-    }
     __syncthreads();
-    const size_t act = (size_t)m * v.depth * n * kW;  // per member: depth x [n][256]
-    layer_fwd<true>(W, b, kIn, xs, kLdX, h0, t.h + act, t.ds + act, row0, n);
+    // keep the normalised input tile (feature-major) for the first layer's weight gradient
+    for (int j = threadIdx.x; j < kR * kIn; j += blockDim.x) {
+        const int c = j / kR, r = j % kR;
+        if (row0 + r < ld) t.x16[(size_t)m * kIn * ld + (size_t)c * ld + row0 + r] = xs[r * kLdX + c];
+    }
+    const size_t act = (size_t)m * v.depth * n * kW;   // SiLU': per member depth x [n][256]
+    const size_t hact = (size_t)m * v.depth * kW * ld; // activations: per member depth x [256][ld]
+    layer_fwd<true>(W, b, kIn, xs, kLdX, h0, t.h + hact, t.ds + act, row0, n, ld);
     __bf16 *hin = h0, *hout = h1;
     for (int l = 1; l < v.depth; ++l) {
         __syncthreads();
         layer_fwd<true>(W + (size_t)kW * kIn + (size_t)(l - 1) * kW * kW, b + l * kW, kW, hin, kLd, hout,
-                        t.h + act + (size_t)l * n * kW, t.ds + act + (size_t)l * n * kW, row0, n);
+                        t.h + hact + (size_t)l * kW * ld, t.ds + act + (size_t)l * n * kW, row0, n, ld);
         __bf16 *tmp = hin; hin = hout; hout = tmp;
     }
     __syncthreads();
@@ -421,20 +426,26 @@ __global__ __launch_bounds__(kThreads) void sur_train_bwd(NetView v, TrainView t
     const int64_t n = t.batch;
     const int64_t row0 = (int64_t)blockIdx.x * kR;
     const int L = v.depth;
-    const size_t act = (size_t)m * L * n * kW;
+    const int64_t ld = t.ld;
+    const size_t act = (size_t)m * L * n * kW;      // SiLU' (row-major)
+    const size_t dact = (size_t)m * L * kW * ld;    // deltas (feature-major)
     const float *wout = v.wout + (size_t)m * kW;
     // top delta
     {
         const float *ds = t.ds + act + (size_t)(L - 1) * n * kW;
-        __bf16 *dg = t.delta + act + (size_t)(L - 1) * n * kW;
+        __bf16 *dg = t.delta + dact + (size_t)(L - 1) * kW * ld;
         for (int j = threadIdx.x; j < kR * kW; j += blockDim.x) {
             const int r = j / kW, c = j % kW;
             const int64_t row = row0 + r;
             float d = 0.0f;
             if (row < n) d = t.g[(size_t)m * n + row] * wout[c] * ds[row * kW + c];
-            const __bf16 db = (__bf16)d;
-            d0[r * kLd + c] = db;
-            if (row < n) dg[row * kW + c] = db;
+            d0[r * kLd + c] = (__bf16)d;
+        }
+        __syncthreads();
+        // feature-major copy for the weight gradient (rows [n, ld) are zero)
+        for (int j = threadIdx.x; j < kR * kW; j += blockDim.x) {
+            const int c = j / kR, r = j % kR;
+            if (row0 + r < ld) dg[(size_t)c * ld + row0 + r] = d0[r * kLd + c];
         }
     }
     const __bf16 *WT = v.WT + (size_t)m * v.w_stride;
@@ -464,7 +475,7 @@ __global__ __launch_bounds__(kThreads) void sur_train_bwd(NetView v, TrainView t
                 for (int bb = 0; bb < 4; ++bb) acc[a][bb] = mfma(wa[a], hb[bb], acc[a][bb]);
         }
         const float *ds = t.ds + act + (size_t)(l - 1) * n * kW;
-        __bf16 *dg = t.delta + act + (size_t)(l - 1) * n * kW;
+        __bf16 *dg = t.delta + dact + (size_t)(l - 1) * kW * ld;
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -481,88 +492,110 @@ __global__ __launch_bounds__(kThreads) void sur_train_bwd(NetView v, TrainView t
                     dv[2] = (__bf16)(acc[a][bb][4 * g + 2] * dsv.z);
                     dv[3] = (__bf16)(acc[a][bb][4 * g + 3] * dsv.w);
                     *reinterpret_cast<bf16x4 *>(dout + r * kLd + k) = dv;
-                    if (row < n) *reinterpret_cast<bf16x4 *>(dg + row * kW + k) = dv;
+                    if (row < ld) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) dg[(size_t)(k + q) * ld + row] = dv[q];
+                    }
                 }
             }
         __bf16 *tmp = din; din = dout; dout = tmp;
     }
 }
 
-// Weight gradients, split over groups of kWgChunks row tiles: dW_l[o][i] += sum_rows
-// delta_l[row][o] x_{l-1}[row][i], with x_0 the (padded) input and x_l the activation of
-// layer l; db_l[o] += sum_rows delta_l[row][o].  blockIdx.x = row group, blockIdx.y =
-// member * depth + layer.  Tiles are transposed into LDS so both MFMA operands read 8
-// consecutive rows; each workgroup adds its partial sums with one atomic per element.
-constexpr int kWgChunks = 8;
-
+// Weight and bias gradients of the hidden layers: dW_l[o][i] = sum over rows
+// of delta_l[row][o] x_l[row][i] (x_0 the inputs, x_l = h_{l-1}), db_l[o] =
+// sum over rows of delta_l[row][o].  One workgroup per 64 x 64 block (o, i) of
+// one layer of one member (layer 0 has 32 inputs); its 4 waves split the rows,
+// each accumulating the block with MFMAs whose fragments are 16-byte reads of
+// the feature-major deltas and activations (rows contiguous, so no transpose),
+// the next step's fragments in flight; the waves' partial blocks are added
+// through LDS and stored by one wave (each gradient entry has one writer).
+constexpr int kWgBlock = 64;
 __global__ __launch_bounds__(kThreads) void sur_train_wgrad(NetView v, TrainView t) {
     extern __shared__ __align__(16) unsigned char smem[];
+    float *part = reinterpret_cast<float *>(smem);     // [3 waves][64 entries][64 lanes]
     const int m = blockIdx.y / v.depth, l = blockIdx.y % v.depth;
-    const int64_t n = t.batch;
     const int Kin = l == 0 ? kIn : kW;
-    constexpr int kLt = kR + 8;                        // LDS stride of transposed tiles
-    __bf16 *dT = reinterpret_cast<__bf16 *>(smem);     // [256][kR]
-    __bf16 *xT = dT + kW * kLt;                        // [128][kR] (one block of inputs)
-    const size_t act = (size_t)m * v.depth * n * kW;
-    const __bf16 *dg = t.delta + act + (size_t)l * n * kW;
-    const __bf16 *xg = l == 0 ? t.x16 + (size_t)m * n * kIn : t.h + act + (size_t)(l - 1) * n * kW;
+    const int nib = (Kin + kWgBlock - 1) / kWgBlock;
+    const int tile = blockIdx.x;
+    if (tile >= (kW / kWgBlock) * nib) return;        // the grid is sized for the widest layer
+    const int o0 = (tile / nib) * kWgBlock, i0 = (tile % nib) * kWgBlock;
+    const int nsub = (Kin - i0 < kWgBlock ? Kin - i0 : kWgBlock) / 32;   // 32-wide input blocks: 2, or 1
+    const int64_t ld = t.ld;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int half = lane >> 5, l32 = lane & 31;
-    float *gW = t.grad + (size_t)m * v.p_stride + (l == 0 ? 0 : (size_t)kW * kIn + (size_t)(l - 1) * kW * kW);
-    float *gb = t.grad + (size_t)m * v.p_stride + v.off_b + (size_t)l * kW;
-    float bsum = 0.0f;                                 // bias partial of feature threadIdx.x
-    for (int ib = 0; ib < Kin; ib += 128) {
-        const int width = Kin - ib < 128 ? Kin - ib : 128;
-        const int nb = width / 32;
-        f32x16 acc[2][4];
+    const __bf16 *dT = t.delta + ((size_t)m * v.depth + l) * kW * ld;
+    const __bf16 *xT = l == 0 ? t.x16 + (size_t)m * kIn * ld : t.h + ((size_t)m * v.depth + (l - 1)) * kW * ld;
+    const __bf16 *a0p = dT + (size_t)(o0 + l32) * ld + 8 * half;
+    const __bf16 *a1p = a0p + (size_t)32 * ld;
+    const __bf16 *b0p = xT + (size_t)(i0 + l32) * ld + 8 * half;
+    const __bf16 *b1p = nsub == 2 ? b0p + (size_t)32 * ld : b0p;
+    // this wave's rows: a contiguous quarter of the 16-row steps
+    const int64_t steps = ld / 16, per = (steps + kPredictWaves - 1) / kPredictWaves;
+    const int64_t s0 = wave * per, s1 = s0 + per < steps ? s0 + per : steps;
+    f32x16 acc[2][2];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int bb = 0; bb < 4; ++bb) acc[a][bb] = f32x16{};
-        for (int ch = 0; ch < kWgChunks; ++ch) {
-            const int64_t row0 = ((int64_t)blockIdx.x * kWgChunks + ch) * kR;
-            if (row0 >= n) break;
-            __syncthreads();
-            for (int j = threadIdx.x; j < kR * kW; j += blockDim.x) {
-                const int r = j / kW, c = j % kW;
-                dT[c * kLt + r] = row0 + r < n ? dg[(row0 + r) * kW + c] : (__bf16)0.0f;
-            }
-            for (int j = threadIdx.x; j < kR * width; j += blockDim.x) {
-                const int r = j / width, c = j % width;
-                xT[c * kLt + r] = row0 + r < n ? xg[(row0 + r) * Kin + ib + c] : (__bf16)0.0f;
-            }
-            __syncthreads();
-            if (ib == 0)
-                for (int r = 0; r < kR; ++r) bsum += (float)dT[threadIdx.x * kLt + r];
-            for (int kk = 0; kk < kR; kk += 16) {
-                bf16x8 da[2], xb[4];
-#pragma unroll
-                for (int a = 0; a < 2; ++a)
-                    da[a] = *reinterpret_cast<const bf16x8 *>(dT + (wave * 64 + a * 32 + l32) * kLt + kk + 8 * half);
-#pragma unroll
-                for (int bb = 0; bb < 4; ++bb)
-                    if (bb < nb) xb[bb] = *reinterpret_cast<const bf16x8 *>(xT + (bb * 32 + l32) * kLt + kk + 8 * half);
-#pragma unroll
-                for (int a = 0; a < 2; ++a)
-#pragma unroll
-                    for (int bb = 0; bb < 4; ++bb)
-                        if (bb < nb) acc[a][bb] = mfma(da[a], xb[bb], acc[a][bb]);
-            }
+        for (int b = 0; b < 2; ++b) acc[a][b] = f32x16{};
+    if (s0 < s1) {
+        bf16x8 fa0 = *reinterpret_cast<const bf16x8 *>(a0p + s0 * 16), fa1 = *reinterpret_cast<const bf16x8 *>(a1p + s0 * 16);
+        bf16x8 fb0 = *reinterpret_cast<const bf16x8 *>(b0p + s0 * 16), fb1 = *reinterpret_cast<const bf16x8 *>(b1p + s0 * 16);
+        for (int64_t st = s0; st < s1; ++st) {
+            const int64_t nx = (st + 1 < s1 ? st + 1 : st) * 16;
+            const bf16x8 na0 = *reinterpret_cast<const bf16x8 *>(a0p + nx), na1 = *reinterpret_cast<const bf16x8 *>(a1p + nx);
+            const bf16x8 nb0 = *reinterpret_cast<const bf16x8 *>(b0p + nx), nb1 = *reinterpret_cast<const bf16x8 *>(b1p + nx);
+            acc[0][0] = mfma(fa0, fb0, acc[0][0]);
+            acc[1][0] = mfma(fa1, fb0, acc[1][0]);
+            acc[0][1] = mfma(fa0, fb1, acc[0][1]);
+            acc[1][1] = mfma(fa1, fb1, acc[1][1]);
+            fa0 = na0; fa1 = na1; fb0 = nb0; fb1 = nb1;
         }
+    }
+    // add the waves' blocks: waves 1..3 through LDS into wave 0
+    if (wave > 0) {
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int bb = 0; bb < 4; ++bb) {
-                if (bb >= nb) continue;
-                const int i = ib + bb * 32 + l32;
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) part[((wave - 1) * 64 + (a * 2 + b) * 16 + r) * 64 + lane] = acc[a][b][r];
+    }
+    __syncthreads();
+    if (wave == 0) {
+        float *gW = t.grad + (size_t)m * v.p_stride + (l == 0 ? 0 : (size_t)kW * kIn + (size_t)(l - 1) * kW * kW);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                if (b >= nsub) continue;
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                    const int o = wave * 64 + a * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-                    atomicAdd(&gW[(size_t)o * Kin + i], acc[a][bb][r]);
+                    float sum = acc[a][b][r];
+#pragma unroll
+                    for (int w = 0; w < kPredictWaves - 1; ++w) sum += part[(w * 64 + (a * 2 + b) * 16 + r) * 64 + lane];
+                    const int o = o0 + a * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                    gW[(size_t)o * Kin + i0 + b * 32 + l32] = sum;
                 }
             }
     }
-    atomicAdd(&gb[threadIdx.x], bsum);
+    // bias gradient of this o block (the i0 = 0 workgroup): thread = (feature, quarter of the rows)
+    if (i0 == 0) {
+        __syncthreads();
+        const int o = o0 + (threadIdx.x & 63), q = threadIdx.x >> 6;
+        const int64_t r0 = (ld / 8) * q / kPredictWaves * 8, r1 = (ld / 8) * (q + 1) / kPredictWaves * 8;
+        float sum = 0.0f;
+        for (int64_t r = r0; r < r1; r += 8) {
+            const bf16x8 d = *reinterpret_cast<const bf16x8 *>(dT + (size_t)o * ld + r);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) sum += (float)d[e];
+        }
+        part[threadIdx.x] = sum;
+        __syncthreads();
+        if (threadIdx.x < 64)
+            t.grad[(size_t)m * v.p_stride + v.off_b + (size_t)l * kW + o] =
+                part[threadIdx.x] + part[threadIdx.x + 64] + part[threadIdx.x + 128] + part[threadIdx.x + 192];
+    }
 }
 
 // Output-layer gradients: dw_out[c] = sum_rows g h_top[c], db_out = sum_rows g.
@@ -570,12 +603,12 @@ __global__ void sur_train_outgrad(NetView v, TrainView t) {
     const int m = blockIdx.y;
     const int64_t n = t.batch;
     const int c = threadIdx.x;
-    const size_t act = (size_t)m * v.depth * n * kW + (size_t)(v.depth - 1) * n * kW;
+    const size_t hact = ((size_t)m * v.depth + (v.depth - 1)) * kW * t.ld + (size_t)c * t.ld;  // feature c, top layer
     const int64_t r0 = (int64_t)blockIdx.x * 256, r1 = r0 + 256 < n ? r0 + 256 : n;
     float s = 0.0f, sg = 0.0f;
     for (int64_t r = r0; r < r1; ++r) {
         const float g = t.g[(size_t)m * n + r];
-        s += g * (float)t.h[act + r * kW + c];
+        s += g * (float)t.h[hact + r];
         sg += g;
     }
     float *gp = t.grad + (size_t)m * v.p_stride;
@@ -644,7 +677,7 @@ __global__ void sur_step_inc(unsigned long long *step) {
 size_t predict_lds() { return (size_t)kR * kLdX * 2 + (size_t)kR * kLd * 2 + (size_t)kPredictWaves * kR * sizeof(float); }
 size_t train_fwd_lds() { return (size_t)kR * kLdX * 2 + (size_t)2 * kR * kLd * 2; }
 size_t bwd_lds() { return (size_t)2 * kR * kLd * 2; }
-size_t wgrad_lds() { return (size_t)(kW + 128) * (kR + 8) * 2; }
+size_t wgrad_lds() { return (size_t)(kPredictWaves - 1) * 64 * 64 * sizeof(float); }
 
 hipError_t configure() {
     hipError_t e;
@@ -691,7 +724,7 @@ hipError_t launch_train_step(const NetView &v, const TrainView &t, const float *
     const int M = v.members;
     const bool gather = X != nullptr;
     const unsigned blocks = (unsigned)((t.batch + kR - 1) / kR);
-    const unsigned groups = (unsigned)((t.batch + (int64_t)kR * kWgChunks - 1) / ((int64_t)kR * kWgChunks));
+    const unsigned groups = (unsigned)((kW / kWgBlock) * (kW / kWgBlock));   // blocks of the widest layer
     if (gather) hipLaunchKernelGGL(sur_gather, dim3(256), dim3(256), 0, s, X, y, n_data, t, step, seed, M);
     hipLaunchKernelGGL(sur_zero, dim3(1), dim3(64), 0, s, t.loss, (size_t)M);
     hipLaunchKernelGGL(sur_train_fwd, dim3(blocks, M), dim3(kThreads), train_fwd_lds(), s, v, t);

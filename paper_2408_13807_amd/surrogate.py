@@ -267,22 +267,28 @@ def model_errors(T: np.ndarray, T_ref: np.ndarray, row_off: np.ndarray, stat: st
     return out
 
 
-def error_summary(T_sur: np.ndarray, T_ire: np.ndarray, T_ref: np.ndarray, row_off: np.ndarray,
-                  accepted: np.ndarray, limit: float = 0.02) -> dict:
-    """Fractions of models within `limit` of the reference by each per-model
-    statistic, for the surrogate on the models it accepts, for every model
-    after the fallback (accepted: surrogate, others: IRE), and for IRE alone."""
+def error_summary(T_sur: np.ndarray, T_ref: np.ndarray, row_off: np.ndarray, accepted: np.ndarray,
+                  others: dict | None = None, limit: float = 0.02) -> dict:
+    """Fractions of models within `limit` of the reference T_ref by each
+    per-model statistic (worst shell, 95th percentile, median of the shells'
+    relative errors): the surrogate on every model and on the models it
+    accepts, and each tracer run in `others` (name -> T) on every model; with
+    an "ire_1x" entry also every model after the fallback (accepted models from
+    the surrogate, the others from that run)."""
+    others = others or {}
     out = {}
     for stat in ("max", "p95", "median"):
         e_s = model_errors(T_sur, T_ref, row_off, stat)
-        e_i = model_errors(T_ire, T_ref, row_off, stat)
-        e_f = np.where(accepted, e_s, e_i)
-        out[stat] = dict(
-            surrogate_all=float(np.mean(e_s <= limit)),
-            surrogate_accepted=float(np.mean(e_s[accepted] <= limit)) if accepted.any() else None,
-            after_fallback=float(np.mean(e_f <= limit)),
-            ire_alone=float(np.mean(e_i <= limit)),
-            median_error_surrogate_accepted=float(np.median(e_s[accepted])) if accepted.any() else None,
-            median_error_after_fallback=float(np.median(e_f)),
-            median_error_ire_alone=float(np.median(e_i)))
+        row = dict(surrogate_all=float(np.mean(e_s <= limit)),
+                   surrogate_accepted=float(np.mean(e_s[accepted] <= limit)) if accepted.any() else None,
+                   median_error_surrogate_accepted=float(np.median(e_s[accepted])) if accepted.any() else None)
+        for name, T in others.items():
+            e = model_errors(T, T_ref, row_off, stat)
+            row[name] = float(np.mean(e <= limit))
+            row[f"median_error_{name}"] = float(np.median(e))
+            if name == "ire_1x":
+                e_f = np.where(accepted, e_s, e)
+                row["after_fallback"] = float(np.mean(e_f <= limit))
+                row["median_error_after_fallback"] = float(np.median(e_f))
+        out[stat] = row
     return out

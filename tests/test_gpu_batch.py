@@ -173,10 +173,19 @@ def test_batch_matches_oracle(ire, params):
 def test_batch_graph_replays(ire, params):
     import torch
     models = pick(params, 16, seed=3)
-    b = ire.batch_from_workloads(params, models, package_scale=0.01)
+    scale = 0.01
+    b = ire.batch_from_workloads(params, models, package_scale=scale)
     b.set_options(use_graph=0)
     b.run()
     eager = b.results()
+    # 16 single-model runs of every model: the reference each replay is held to
+    refs = []
+    for m in models:
+        mm = wl.batch_model(params, m)
+        key = "n_ps" if params["central"][m] else "n_ext"
+        npk = max(1, round(int(params["n_pkg"][m]) * scale))
+        runs = [ire.run_model(mm, seed=400 + k, **{key: npk}) for k in range(16)]
+        refs.append(([x["T"] for x in runs], [x["A"] for x in runs]))
     b.set_options(use_graph=1)
     for rep in range(3):
         b.run()
@@ -184,9 +193,12 @@ def test_batch_graph_replays(ire, params):
         s = r["stats"]
         assert s["n_launch"] == eager["stats"]["n_launch"]
         assert abs((s["escaped"] + s["ffi_escaped"] + s["terminated"]) / s["L_total"] - 1) < 1e-9
-        # replays start from zero: the same mean temperature level as the eager run
-        ratio = r["T"] / eager["T"]
-        assert abs(np.median(ratio) - 1) < 0.01
+        # every replay starts from zero and is a full run: each model within the
+        # statistical bound of its single-model runs, and as much energy absorbed as the eager run
+        for j, (m, T) in enumerate(zip(models, split(b, r["T"]))):
+            ok, f = mc_stats.compare_runs(T, refs[j][0], refs[j][1], name=f"replay {rep} model {m}")
+            assert ok, (rep, m, f)
+        assert abs(r["A"].sum() / eager["A"].sum() - 1) < 0.02
         # eager work and a synchronisation between replays
         x = torch.ones(1 << 20, device="cuda")
         torch.cuda.synchronize()

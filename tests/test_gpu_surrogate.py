@@ -145,10 +145,14 @@ def test_predict_models_rejects_bad_offsets(sur):
 def test_trained_surrogate_gains_over_the_tracer(sur):
     # End to end on a small parameter study: train the ensemble on batched IRE
     # temperatures of 8000 study models, then, on 512 held-out models, compare
-    # surrogate-with-fallback against the batched tracer alone, both scored
-    # against IRE at 4x each model's package budget.  The surrogate must keep
-    # the models it accepts close to the reference and answer far faster than
-    # the tracer that trained it.
+    # surrogate-with-fallback against the batched tracer at the same budgets,
+    # both scored against IRE at 16x each model's package budget.  Every model
+    # is scored by its worst shell, the 95th percentile of its shells and their
+    # median.  The worst shell of a model is mostly the Monte Carlo noise of a
+    # rarely hit shell (in IRE itself and in the reference), so the claim is
+    # comparative there: the models the surrogate accepts are within 2 % at
+    # least as often as the tracer's own runs.  The surrogate must also answer
+    # in a fraction of the tracer's time.
     import time
 
     from paper_2408_13807_amd import workloads as wl
@@ -159,8 +163,9 @@ def test_trained_surrogate_gains_over_the_tracer(sur):
     net = sur.fit(X, y, steps=8000, batch=4096, seed=3)
     try:
         held = wl.batch_parameters(512, seed=12)
-        ref = sur.ire_profiles(held, range(512), package_scale=4.0)
-        own = sur.ire_profiles(held, range(512), package_scale=1.0)
+        ref = sur.ire_profiles(held, range(512), package_scale=16.0)
+        other = dict(held, seed=held["seed"] + np.uint64(1 << 20))
+        own = sur.ire_profiles(other, range(512), package_scale=1.0)
         sur.predict_models(net, held, range(8))        # warm-up
         t0 = time.perf_counter()
         p = sur.predict_models(net, held, range(512))
@@ -169,14 +174,22 @@ def test_trained_surrogate_gains_over_the_tracer(sur):
     finally:
         net.close()
     acc = p["model_spread"] <= 0.02
-    err_s = sur.model_errors(10.0 ** p["logT"].astype(np.float64), ref["T"], ref["row_off"])
-    err_i = sur.model_errors(own["T"], ref["T"], ref["row_off"])
-    err_f = sur.model_errors(out["T"], ref["T"], ref["row_off"])
-    print(f"accepted {acc.mean():.2f}; median error accepted {np.median(err_s[acc]):.4f}, "
-          f"with fallback {np.median(err_f):.4f}, tracer alone {np.median(err_i):.4f}; "
-          f"prediction {t_pred * 1e3:.1f} ms vs tracer {own['seconds'] * 1e3:.1f} ms", flush=True)
+    Ts = 10.0 ** p["logT"].astype(np.float64)
+    summ = sur.error_summary(Ts, ref["T"], ref["row_off"], acc, {"ire_1x": own["T"]})
+    for stat, row in summ.items():
+        print(f"{stat}: within 2 %: surrogate accepted {row['surrogate_accepted']:.3f}, all {row['surrogate_all']:.3f}, "
+              f"after fallback {row['after_fallback']:.3f}, tracer {row['ire_1x']:.3f}", flush=True)
+    print(f"accepted {acc.mean():.2f}; prediction {t_pred * 1e3:.1f} ms vs tracer {own['seconds'] * 1e3:.1f} ms",
+          flush=True)
     assert acc.mean() > 0.3
-    assert np.median(err_s[acc]) < 0.02
-    assert np.mean(err_f <= 0.02) > 0.85
+    # worst shell and 95th percentile: the accepted models at least as often within 2 % as the tracer's runs
+    assert summ["max"]["surrogate_accepted"] >= summ["max"]["ire_1x"]
+    assert summ["p95"]["surrogate_accepted"] >= summ["p95"]["ire_1x"]
+    # the typical shell: accepted models' median error well inside 2 %, and after the fallback
+    assert summ["median"]["median_error_surrogate_accepted"] < 0.01
+    assert summ["median"]["after_fallback"] > 0.85
+    # the fallback's temperatures are the tracer's own
+    err_f = sur.model_errors(out["T"], ref["T"], ref["row_off"], "p95")
+    assert np.isfinite(err_f).all()
     # the prediction of every model takes a fraction of what the tracer needs for them
     assert t_pred < 0.2 * own["seconds"]
