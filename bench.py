@@ -122,8 +122,8 @@ def bench_batch(args) -> dict:
     torch.cuda.set_device(0)
     b = ire.batch_from_workloads(params, package_scale=scale)
     # schedule knobs for experiments (defaults otherwise)
-    knobs = {k: int(os.environ[e]) for k, e in (("aggregate", "IRE_BENCH_AGG"), ("batch", "IRE_BENCH_BATCH"))
-             if e in os.environ}
+    knobs = {k: int(os.environ[e]) for k, e in (("aggregate", "IRE_BENCH_AGG"), ("batch", "IRE_BENCH_BATCH"),
+                                                ("item_packages", "IRE_BENCH_ITEM")) if e in os.environ}
     if knobs:
         b.set_options(**knobs)
     n_pkg = int(sum(max(1, round(int(x) * scale)) for x in params["n_pkg"]))
