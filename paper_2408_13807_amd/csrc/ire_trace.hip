@@ -552,7 +552,12 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
         KRec nxk{};
         if constexpr (KRHO) nxk = rk[pn - sh];
         const R arg = (inward ? cur.r2_in : cur.r2_out) - b2;
-        const R sq = P<R>::sqrt_(arg > (R)0 ? arg : (R)0);
+        // arg >= 0 but for rounding at a tangent point or on a boundary: the FP32
+        // kernels take |arg| (a free source modifier of the square root, within
+        // rounding of the clamp), the FP64 ones clamp at 0
+        R sq;
+        if constexpr (kLoose) sq = P<R>::sqrt_(__builtin_fabsf(arg));
+        else sq = P<R>::sqrt_(arg > (R)0 ? arg : (R)0);
         const R tn = inward ? -sq : sq;
         const R ds = cur.rho * (tn - t);
         bool cross = ds < sig;
