@@ -18,3 +18,10 @@ def orc():
     import oracle
     oracle.build(force=False)
     return oracle
+
+
+def pytest_terminal_summary(terminalreporter):
+    mc = sys.modules.get("mc_stats")
+    if mc is not None and mc.KS_PVALUES:
+        name, p = min(mc.KS_PVALUES, key=lambda x: x[1])
+        terminalreporter.write_line(f"z-score distribution tests: {len(mc.KS_PVALUES)}, smallest p = {p:.3g} ({name})")

@@ -13,7 +13,11 @@ reliably nor bounds its tails.  The check therefore:
     uncertainty of the R-run mean;
   * asks for |T - <T>| <= max(1 %, 3 sigma) in at least `frac` of the shells;
   * asks for |T - <T>| <= max(1 %, 6 sigma) in every shell in the Gaussian
-    regime, i.e. with an effective deposit count (<A> / sigma_A)^2 >= n_eff.
+    regime, i.e. with an effective deposit count (<A> / sigma_A)^2 >= n_eff;
+  * with an ensemble of runs at hand (compare_runs), asks that the run's
+    signed z-scores follow the distribution of the reference runs' own
+    leave-one-out z-scores (two-sample Kolmogorov-Smirnov, p >= 1e-6), so a
+    shift of many shells by a fraction of a sigma also fails.
 
 On synthetic compound-Poisson shells (tests/test_mc_stats.py) a run from the
 same distribution fails this about once in 1500 comparisons, and a 5 % error
@@ -28,8 +32,10 @@ def pooled_sigma(mean, std, half_window: int = 3) -> np.ndarray:
     mean = np.asarray(mean, np.float64)
     std = np.asarray(std, np.float64)
     rel = np.where(mean > 0, std / np.where(mean > 0, mean, 1.0), 0.0)
-    n = len(rel)
-    med = np.array([np.median(rel[max(0, i - half_window):i + half_window + 1]) for i in range(n)])
+    # median over the window [i - half_window, i + half_window], cut at the ends
+    pad = np.full(len(rel) + 2 * half_window, np.nan)
+    pad[half_window:half_window + len(rel)] = rel
+    med = np.nanmedian(np.lib.stride_tricks.sliding_window_view(pad, 2 * half_window + 1), axis=1)
     return np.maximum(std, med * mean)
 
 
@@ -55,12 +61,64 @@ def compare(T, T_mean, T_std, A_mean, A_std, R: int, frac: float = 0.95, rel: fl
     return passed, float(ok3.mean())
 
 
-def compare_runs(T, T_runs, A_runs, **kw) -> tuple[bool, float]:
-    """compare() against an ensemble given as [R, n] arrays of T and A."""
+# (comparison name, p-value) of every z-score distribution test of the session
+KS_PVALUES: list[tuple[str, float]] = []
+
+
+def z_scores(T, T_mean, T_std, R: int) -> np.ndarray:
+    """Signed per-shell deviations in units of compare()'s sigma, over the
+    shells whose sigma is not zero."""
+    sig = pooled_sigma(T_mean, T_std) * np.sqrt(1.0 + 1.0 / R)
+    live = sig > 0
+    return ((np.asarray(T, np.float64) - T_mean) / np.where(live, sig, 1.0))[live]
+
+
+def z_shift_pvalue(T, T_runs) -> float:
+    """p-value of a two-sample Kolmogorov-Smirnov test of the run's z-scores
+    against a null drawn from the reference runs themselves: each reference
+    run's z-scores against the other R-1 runs.  The null therefore has the
+    same discreteness, skew and shell-to-shell correlation as the run's own
+    z-scores would if the run came from the reference distribution, and a
+    systematic shift or widening over many shells (each one too small for the
+    per-shell rules) moves the run's z-scores away from it."""
+    from scipy.stats import ks_2samp, kstwobign
+    T_runs = np.asarray(T_runs, np.float64)
+    R = len(T_runs)
+    z = z_scores(T, T_runs.mean(0), T_runs.std(0, ddof=1), R)
+    null = []
+    for k in range(R):
+        rest = np.delete(T_runs, k, axis=0)
+        null.append(z_scores(T_runs[k], rest.mean(0), rest.std(0, ddof=1), R - 1))
+    if len(z) == 0 or min(len(x) for x in null) == 0:
+        return 1.0
+    D = ks_2samp(z, np.concatenate(null)).statistic
+    # Neighbouring shells share packages, so their z-scores are correlated and
+    # the statistic spreads wider than the Kolmogorov law for independent
+    # samples gives.  Its scale is therefore measured on the null itself: each
+    # reference run's distance from the pool of the others, whose median sets
+    # the effective sample size (the Kolmogorov law's median is 0.8276).
+    Dk = [ks_2samp(null[k], np.concatenate(null[:k] + null[k + 1:])).statistic for k in range(R)]
+    med = float(np.median(Dk))
+    if med <= 0:
+        return 1.0 if D <= 0 else 0.0
+    return float(kstwobign.sf(D * kstwobign.median() / med))
+
+
+def compare_runs(T, T_runs, A_runs, ks_alpha: float = 1e-6, **kw) -> tuple[bool, float]:
+    """compare() against an ensemble given as [R, n] arrays of T and A, and the
+    z-score distribution test (z_shift_pvalue) at level ks_alpha."""
     T_runs = np.asarray(T_runs, np.float64)
     A_runs = np.asarray(A_runs, np.float64)
-    return compare(T, T_runs.mean(0), T_runs.std(0, ddof=1), A_runs.mean(0), A_runs.std(0, ddof=1),
-                   len(T_runs), **kw)
+    ok, f = compare(T, T_runs.mean(0), T_runs.std(0, ddof=1), A_runs.mean(0), A_runs.std(0, ddof=1),
+                    len(T_runs), **kw)
+    if ks_alpha > 0:
+        p = z_shift_pvalue(T, T_runs)
+        KS_PVALUES.append((kw.get("name", ""), p))
+        if p < ks_alpha:
+            print(f"{kw.get('name', '')}: z-scores differ in distribution from the reference runs' own "
+                  f"(KS p = {p:.2e})")
+            ok = False
+    return ok, f
 
 
 def zero_deposit_failures(A, A_ref_mean, eps, p_max: float = 1e-6) -> list[int]:

@@ -64,3 +64,39 @@ def test_zero_deposit_check():
     A = rng.poisson(lam) * eps
     A[3] = 0.0
     assert mc_stats.zero_deposit_failures(A, lam * eps, eps) == [3]
+
+
+def draw_correlated(rng, lam, runs, w=8):
+    """As draw(), with every deposit shared by w neighbouring shells (packages
+    that cross several shells), so neighbouring shells' values correlate."""
+    lp = np.concatenate([lam, lam[:w]])
+    n = rng.poisson(lp / w, size=(runs, len(lam) + w))
+    n = np.stack([n[:, i:i + len(lam)] for i in range(w)]).sum(0)
+    A = rng.gamma(np.maximum(n, 1), 1.0) * (n > 0)
+    T = np.maximum(30.0 * (A / np.maximum(lam, 1e-9)) ** (1 / 5.8), 3.0)
+    return T, A
+
+
+def test_z_distribution_test_null_calibration():
+    # runs from the reference distribution, independent or correlated shells:
+    # the z-score test stays far from its 1e-6 level
+    rng = np.random.default_rng(12)
+    lam = 10 ** rng.uniform(-0.3, 4, size=200)
+    for drawer in (draw, draw_correlated):
+        p = [mc_stats.z_shift_pvalue(T[0], T[1:]) for T, _ in (drawer(rng, lam, 17) for _ in range(150))]
+        assert min(p) > 1e-5, (drawer.__name__, min(p))
+        assert 0.2 < np.median(p) < 0.9, (drawer.__name__, np.median(p))
+
+
+def test_detects_a_shift_the_per_shell_rules_pass():
+    # every shell moved by one sigma: within the 95 % / 6 sigma rules, caught
+    # by the z-score distribution
+    rng = np.random.default_rng(13)
+    lam = 10 ** rng.uniform(1, 4, size=300)
+    caught = 0
+    for _ in range(20):
+        T, A = draw(rng, lam, 17)
+        t = T[0] + T[1:].std(0, ddof=1)
+        assert mc_stats.compare_runs(t, T[1:], A[1:], ks_alpha=0)[0]
+        caught += not mc_stats.compare_runs(t, T[1:], A[1:])[0]
+    assert caught == 20
