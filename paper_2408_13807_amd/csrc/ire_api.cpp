@@ -213,8 +213,11 @@ int trace_launch_setup(ire_model *m, int replicas, uint64_t n_ext, uint64_t n_ps
     p.k_A_rho = m->opt.k_A_rho; p.rkf = m->rkf.p; p.rkd = m->rkd.p;
     p.replicas = replicas;
     {
+        // packages a wave takes from the global cursor at a time: about 64 grabs
+        // per wave and launch keep the waves' last grabs short (the launch ends
+        // with its slowest wave), and one grab must cover a whole wave's refill
         const unsigned long long waves = (unsigned long long)grid * (block / 64);
-        unsigned long long c = (n_ext + n_ps) / (waves * 8ull);
+        unsigned long long c = (n_ext + n_ps) / (waves * 64ull);
         p.chunk = std::min<unsigned long long>(std::max<unsigned long long>(c, 64ull), 4096ull);
     }
     p.batch = m->opt.batch > 0 ? m->opt.batch : (agg == 2 ? 52 : (replicas > 1 ? 40 : 64));

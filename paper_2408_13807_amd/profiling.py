@@ -94,7 +94,7 @@ def summary(dbs: list[str]) -> str:
             lines.append("| kernel | calls | total (ms) | average (ms) | % |")
             lines.append("|---|---|---|---|---|")
             for name, calls, tot, avg, pct in rows:
-                lines.append(f"| `{name[:90]}` | {calls} | {tot / 1e3:.1f} | {avg / 1e3:.1f} | {pct:.2f} |")
+                lines.append(f"| `{name[:90]}` | {calls} | {tot / 1e3:.3f} | {avg / 1e3:.4f} | {pct:.2f} |")
             lines.append("")
         cnt = _counters(db)
         if cnt:
