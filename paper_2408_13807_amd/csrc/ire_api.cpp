@@ -123,7 +123,7 @@ int build_tables(ire_model *m) {
 
     std::vector<float> cdff(cdf.begin(), cdf.end()), Gf(G.begin(), G.end()), Df(D.begin(), D.end());
     std::vector<unsigned char> guide;
-    ire::host::build_guides(dt, cdf.data(), K, guide, m->g_lg0, m->g_scale);
+    ire::host::build_guides(dt, guide, m->g_lg0, m->g_scale);
     hipError_t e;
     if ((e = hipSetDevice(m->device)) != hipSuccess) return m->hip_fail(e, "hipSetDevice");
     if ((e = m->shf.upload(shf)) != hipSuccess || (e = m->shd.upload(shd)) != hipSuccess ||
@@ -382,8 +382,8 @@ int ire_set_shells(ire_model *m, int32_t n, const double *r_edges, const double 
 int ire_set_dust(ire_model *m, int32_t K, const double *nu, const double *kappa_abs,
                  const double *albedo, const double *g) {
     if (!m) return IRE_E_INVALID;
-    if (K < 1 || K > ire::kMaxGuideK || !nu || !kappa_abs || !albedo || !g)
-        return m->fail(IRE_E_INVALID, "need 1 <= K <= %d and all dust arrays", ire::kMaxGuideK);
+    if (K < 1 || K > ire::kMaxK || !nu || !kappa_abs || !albedo || !g)
+        return m->fail(IRE_E_INVALID, "need 1 <= K <= %d and all dust arrays", ire::kMaxK);
     if (!finite_all(nu, K) || !finite_all(kappa_abs, K) || !finite_all(albedo, K) || !finite_all(g, K))
         return m->fail(IRE_E_INVALID, "non-finite dust data");
     for (int k = 0; k < K; ++k) {

@@ -184,7 +184,7 @@ int prepare(ire_batch *b) {
 
     std::vector<float> cdff(cdf.begin(), cdf.end()), Gf(b->dt.G.begin(), b->dt.G.end()), Df(b->dt.D.begin(), b->dt.D.end());
     std::vector<unsigned char> guide;
-    ire::host::build_guides(b->dt, cdf.data(), K, guide, b->g_lg0, b->g_scale);
+    ire::host::build_guides(b->dt, guide, b->g_lg0, b->g_scale);
     hipError_t he;
     if ((he = hipSetDevice(b->device)) != hipSuccess) return b->hip_fail(he, "hipSetDevice");
     if (b->opt.k_A_rho && (he = b->rkf.upload(rkf)) != hipSuccess)

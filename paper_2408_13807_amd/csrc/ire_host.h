@@ -104,11 +104,10 @@ inline std::string build_dust_tables(const std::vector<double> &nu, const std::v
     return "";
 }
 
-// Guide tables for the G(T) table and the frequency CDFs (layout in
-// ire_internal.h).  Any start is correct for the device's bidirectional
-// scan; a good start makes the scan one or two steps.
-inline void build_guides(const DustTables &dt, const double *src_cdf /* 2*K */, int K, std::vector<unsigned char> &out,
-                         float &lg0, float &scale) {
+// Guide table for the G(T) table (layout in ire_internal.h).  Any start is
+// correct for the device's bidirectional scan; a good start makes the scan
+// one or two steps.
+inline void build_guides(const DustTables &dt, std::vector<unsigned char> &out, float &lg0, float &scale) {
     const int nt = (int)dt.G.size();
     out.assign(guide_bytes(nt), 0);
     auto count_le = [](const double *t, int n, double x) {
@@ -124,14 +123,6 @@ inline void build_guides(const DustTables &dt, const double *src_cdf /* 2*K */, 
         const double edge = std::exp2(l0 + (scale > 0.0f ? b / (double)scale : 0.0));
         gg[b] = (uint16_t)count_le(dt.G.data(), nt, edge);
     }
-    unsigned char *dg = out.data() + (size_t)nt * 2;
-    for (int j = 0; j < nt; ++j)
-        for (int b = 0; b < kGuide; ++b)
-            dg[(size_t)j * kGuide + b] = (unsigned char)count_le(dt.D.data() + (size_t)j * K, K, (double)b / kGuide);
-    unsigned char *cg = dg + (size_t)nt * kGuide;
-    for (int s = 0; s < 2; ++s)
-        for (int b = 0; b < kGuide; ++b)
-            cg[s * kGuide + b] = (unsigned char)count_le(src_cdf + (size_t)s * K, K, (double)b / kGuide);
 }
 
 // Shell table of one cloud in units of its outer radius: [an empty cavity
@@ -236,7 +227,7 @@ inline std::string check_weights(int use_g_E, double g_E, int use_g_S, double g_
 }
 
 inline std::string check_dust(int K, const double *nu, const double *kabs, const double *albedo, const double *g) {
-    if (K < 1 || K > kMaxGuideK || !nu || !kabs || !albedo || !g) return "need 1 <= K <= 255 and all dust arrays";
+    if (K < 1 || K > kMaxK || !nu || !kabs || !albedo || !g) return "need 1 <= K <= 255 and all dust arrays";
     if (!finite_all(nu, K) || !finite_all(kabs, K) || !finite_all(albedo, K) || !finite_all(g, K))
         return "non-finite dust data";
     for (int k = 0; k < K; ++k) {

@@ -31,16 +31,35 @@ __host__ __device__ inline size_t agg_lds_bytes(int block) {
     const size_t wg = (size_t)kWgSlots * (2 * sizeof(double) + sizeof(unsigned)) + 4 * sizeof(unsigned);
     return (wave > wg ? wave : wg) + 8;
 }
-// Guide tables (cut-point method, Chen & Asau 1974) accelerate the searches
-// of the G(T) table and of the frequency CDFs; the searches stay exact (a
-// bidirectional scan from the guide's start).  Layout of the guide bytes:
-// uint16 gg[n_t] (G table, bins uniform in log2 G), then uint8
-// dg[n_t][kGuide] (re-emission CDF rows, bins uniform in u), then uint8
-// cg[2][kGuide] (source CDFs).
-constexpr int kGuide = 16;
-__host__ __device__ inline size_t guide_bytes(int n_t) { return ((size_t)n_t * 2 + (size_t)n_t * kGuide + 2 * kGuide + 15) / 16 * 16; }
-constexpr int kMaxGuideK = 255;       // frequencies per CDF row a byte guide can index
+// A guide table (cut-point method, Chen & Asau 1974) accelerates the search
+// of the G(T) table; the search stays exact (a bidirectional scan from the
+// guide's start).  Layout of the guide bytes: uint16 gg[n_t], bins uniform in
+// log2 G.  (The frequency CDFs are searched four ways, count_le4.)
+__host__ __device__ inline size_t guide_bytes(int n_t) { return ((size_t)n_t * 2 + 15) / 16 * 16; }
+constexpr int kMaxK = 255;            // frequencies of a model (the API's limit)
 constexpr int kMaxGuideNt = 65535;    // temperature points a 16-bit guide can index
+
+// Number of entries of the non-decreasing table t[0..n) (n >= 1) that are
+// <= x, by a four-way search: each round reads three entries at once (their
+// LDS latencies overlap) and keeps one of four equal parts of the range, so a
+// 64-entry row takes four rounds in every lane.  A lane scanning from a guide
+// start is fast on average, but a wave waits for its longest scan, and the
+// far tails of a spectrum (many frequencies with a tiny share of the power)
+// make some scans long.
+template <typename T, typename X>
+__host__ __device__ inline int count_le4(const T *t, int n, X x) {
+    int step = 1;
+    while (step * 4 <= n) step *= 4;    // the answer, in [0, n], is below 4 * step
+    int pos = 0;
+    for (; step > 0; step >>= 2) {
+        const int q1 = pos + step, q2 = q1 + step, q3 = q2 + step;
+        const X v1 = (X)t[(q1 < n ? q1 : n) - 1];
+        const X v2 = (X)t[(q2 < n ? q2 : n) - 1];
+        const X v3 = (X)t[(q3 < n ? q3 : n) - 1];
+        pos += step * ((int)(q1 <= n && v1 <= x) + (int)(q2 <= n && v2 <= x) + (int)(q3 <= n && v3 <= x));
+    }
+    return pos;
+}
 
 // Shell geometry in units of the outer radius: squared inner and outer radius,
 // density times the outer radius (so kappa * rho_hat * l_hat is an optical depth

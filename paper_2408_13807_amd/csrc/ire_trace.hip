@@ -157,13 +157,6 @@ __device__ __forceinline__ int g_guide(const uint16_t *gg, int n_t, float lg0, f
     return gg[b];
 }
 
-// Guide start for u in (0, 1) in a CDF row with kGuide bins.
-template <typename R>
-__device__ __forceinline__ int cdf_guide(const unsigned char *g, R u) {
-    const int b = (int)(u * (R)kGuide);
-    return g[b < kGuide ? b : kGuide - 1];
-}
-
 // Henyey-Greenstein: cos(theta) by inversion of the cumulative law for uniform
 // u, and the probability density of cos(theta) (Eq. 6).
 template <typename R>
@@ -481,8 +474,6 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
     const int batch = o.batch > 0 ? o.batch : 1;
     const Shell *const sentinel = sh + n_int;
     const uint16_t *const gguide = reinterpret_cast<const uint16_t *>(guide);
-    const unsigned char *const dguide = guide + (size_t)n_t * 2;
-    const unsigned char *const cguide = dguide + (size_t)n_t * kGuide;
 
     unsigned long long pool_next = 0, pool_end = 0;  // wave-uniform
 
@@ -759,9 +750,8 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
             }
             if (launching || absorbing) {
                 const R *tab = launching ? cdf + src * K : D + (size_t)row * K;
-                const unsigned char *gd = launching ? cguide + src * kGuide : dguide + (size_t)row * kGuide;
                 const R u = P<R>::uni(launching ? r1.x : r1.y);
-                k = min(count_le_from(tab, K, u, cdf_guide(gd, u)), K - 1);
+                k = min(count_le4(tab, K, u), K - 1);
             }
             const Dust d = dust[k];
 

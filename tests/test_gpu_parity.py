@@ -340,7 +340,7 @@ def test_invalid_arguments_rejected(ire):
             with pytest.raises(ire.IREError) as e:
                 h.set_options(**bad)
             assert e.value.code == ire.IRE_E_INVALID, bad
-        K = 256                        # guide tables index at most 255 frequencies
+        K = 256                        # the API takes at most 255 frequencies
         nu = np.geomspace(1e12, 1e15, K)
         with pytest.raises(ire.IREError) as e:
             h.set_dust(nu, np.ones(K), np.zeros(K), np.zeros(K))

@@ -97,7 +97,7 @@ int main() {
         cumulative(nu.data(), K, cdf.data() + K);
         std::vector<unsigned char> guide;
         float lg0 = 0, sc = 0;
-        build_guides(dt, cdf.data(), K, guide, lg0, sc);
+        build_guides(dt, guide, lg0, sc);
         if (guide.size() != guide_bytes(nt)) return 5;
         for (double v : dt.G) sum += v;
         ++cases;
