@@ -60,7 +60,7 @@ typedef struct ire_options {
                              workgroup's waves then run their event passes together; fewer than 2^22 shells);
                              -1 (default): 2 with replicas = 1, 1 otherwise */
     int32_t batch;        /* lanes of a wave parked at an event before their events are processed together
-                             (1..64, at most the wave's lanes with packages; 0 = default: 52 with aggregate 2,
+                             (1..64, at most the wave's lanes with packages; 0 = default: 48 with aggregate 2,
                              else 64 with replicas = 1 and 40 otherwise); changes speed, not the distribution
                              of results */
     /* Sect. 2.2, Table 1: weighted sampling.  Reference direction: towards the
@@ -89,7 +89,7 @@ typedef struct ire_options {
                              crossing sweeps at `batch` parked lanes, the others end theirs early and the
                              workgroup runs its event pass; with `quorum` or fewer waves left with packages
                              each wave sweeps to its own batch (1..16; 16: every wave always does; 0 = default:
-                             6); changes speed, not the distribution of results */
+                             3); changes speed, not the distribution of results */
 } ire_options;
 
 typedef struct ire_stats {
@@ -160,8 +160,8 @@ int ire_reset(ire_model *m);
 
 /* Pick the event-pass schedule for this model: time one launch of a sample of
  * the run (at most 2e7 packages in all, split as n_ext : n_ps) for every candidate
- * (with workgroup grouping in FP32: quorum 3, 4, 6, 8 x parked lanes 36, 44,
- * 52; otherwise parked lanes 24, 32, 40, 48, 64), after one untimed launch, and
+ * (with workgroup grouping in FP32: quorum 2, 3, 4, 6 x parked lanes 36, 40,
+ * 44, 48, 52; otherwise parked lanes 24, 32, 40, 48, 64), after one untimed launch, and
  * set the fastest in the handle's options (the other options are kept).
  * Schedules change speed, not the distribution of results.  *quorum and *batch
  * (either may be NULL) receive the choice; the tuning runs synchronously on

@@ -165,8 +165,8 @@ struct TraceLaunch {
 
 int trace_launch_setup(ire_model *m, int replicas, uint64_t n_ext, uint64_t n_ps, TraceLaunch &L) {
     // schedule: with one running total per shell, per-lane or per-wave atomics on the few addresses bound
-    // the launch, and grouping the absorptions of the whole workgroup (its waves pass together, at 52 parked
-    // lanes, or once 6 waves are there) makes the fewest; with accumulator groups the launch is
+    // the launch, and grouping the absorptions of the whole workgroup (its waves pass together, at 48 parked
+    // lanes, or once 3 waves are there) makes the fewest; with accumulator groups the launch is
     // instruction-bound, and per-wave grouping at 40 parked lanes is the better balance
     const int agg = m->opt.aggregate >= 0 ? m->opt.aggregate : (replicas > 1 ? 1 : 2);
     if (agg == 2 && m->rho.size() >= (1u << 22))
@@ -220,8 +220,8 @@ int trace_launch_setup(ire_model *m, int replicas, uint64_t n_ext, uint64_t n_ps
         unsigned long long c = (n_ext + n_ps) / (waves * 64ull);
         p.chunk = std::min<unsigned long long>(std::max<unsigned long long>(c, 64ull), 4096ull);
     }
-    p.batch = m->opt.batch > 0 ? m->opt.batch : (agg == 2 ? 52 : (replicas > 1 ? 40 : 64));
-    p.quorum = m->opt.quorum > 0 ? m->opt.quorum : 6;
+    p.batch = m->opt.batch > 0 ? m->opt.batch : (agg == 2 ? 48 : (replicas > 1 ? 40 : 64));
+    p.quorum = m->opt.quorum > 0 ? m->opt.quorum : 3;
     L.fp64 = fp64;
     L.agg = agg;
     L.grid = grid;
@@ -615,8 +615,8 @@ int ire_tune_schedule(ire_model *m, uint64_t n_ext, uint64_t n_ps, int32_t *quor
     const int agg = m->opt.aggregate >= 0 ? m->opt.aggregate : (m->opt.replicas > 1 ? 1 : 2);
     std::vector<std::pair<int, int>> cand;   // (quorum, batch)
     if (agg == 2 && m->opt.stepping == IRE_FP32) {
-        for (int q : {3, 4, 6, 8})
-            for (int b : {36, 44, 52}) cand.emplace_back(q, b);
+        for (int q : {2, 3, 4, 6})
+            for (int b : {36, 40, 44, 48, 52}) cand.emplace_back(q, b);
     } else {
         for (int b : {24, 32, 40, 48, 64}) cand.emplace_back(m->opt.quorum, b);
     }

@@ -40,18 +40,29 @@ constexpr int kMaxK = 255;            // frequencies of a model (the API's limit
 constexpr int kMaxGuideNt = 65535;    // temperature points a 16-bit guide can index
 
 // Number of entries of the non-decreasing table t[0..n) (n >= 1) that are
-// <= x, by a four-way search: each round reads three entries at once (their
-// LDS latencies overlap) and keeps one of four equal parts of the range, so a
-// 64-entry row takes four rounds in every lane.  A lane scanning from a guide
-// start is fast on average, but a wave waits for its longest scan, and the
-// far tails of a spectrum (many frequencies with a tiny share of the power)
-// make some scans long.
+// <= x, by a four-way search: each round reads several entries at once (their
+// LDS latencies overlap) and keeps one of four equal parts of the range; the
+// first round also tests the range's end, so a 64-entry row takes three
+// rounds (4 + 3 + 3 reads) in every lane.  A lane scanning from a guide start
+// is fast on average, but a wave waits for its longest scan, and the far
+// tails of a spectrum (many frequencies with a tiny share of the power) make
+// some scans long.
 template <typename T, typename X>
 __host__ __device__ inline int count_le4(const T *t, int n, X x) {
     int step = 1;
-    while (step * 4 <= n) step *= 4;    // the answer, in [0, n], is below 4 * step
+    while (step * 4 < n) step *= 4;     // the answer, in [0, n], is at most 4 * step
     int pos = 0;
-    for (; step > 0; step >>= 2) {
+    {
+        int c = 0;
+#pragma unroll
+        for (int j = 1; j <= 4; ++j) {
+            const int q = j * step;
+            const X v = (X)t[(q < n ? q : n) - 1];
+            c += (int)(q <= n && v <= x);
+        }
+        pos = step * c;
+    }
+    for (step >>= 2; step > 0; step >>= 2) {
         const int q1 = pos + step, q2 = q1 + step, q3 = q2 + step;
         const X v1 = (X)t[(q1 < n ? q1 : n) - 1];
         const X v2 = (X)t[(q2 < n ? q2 : n) - 1];
