@@ -60,9 +60,9 @@ typedef struct ire_options {
                              workgroup's waves then run their event passes together; fewer than 2^22 shells);
                              -1 (default): 2 with replicas = 1, 1 otherwise */
     int32_t batch;        /* lanes of a wave parked at an event before their events are processed together
-                             (1..64, at most the wave's lanes with packages; 0 = default: 48 with aggregate 2,
-                             else 64 with replicas = 1 and 40 otherwise); changes speed, not the distribution
-                             of results */
+                             (1..64, at most the wave's lanes with packages; 0 = default: 48 with aggregate 2
+                             (56 with ffi), else 64 with replicas = 1 and 40 otherwise); changes speed, not
+                             the distribution of results */
     /* Sect. 2.2, Table 1: weighted sampling.  Reference direction: towards the
      * centre for packages of the external field, outwards for the point source. */
     int32_t use_g_E;      /* Eq. 6: re-emission cosine about the reference direction from HG(g_E), g_E in (-1,1) */

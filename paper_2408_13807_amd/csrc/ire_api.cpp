@@ -220,7 +220,8 @@ int trace_launch_setup(ire_model *m, int replicas, uint64_t n_ext, uint64_t n_ps
         unsigned long long c = (n_ext + n_ps) / (waves * 64ull);
         p.chunk = std::min<unsigned long long>(std::max<unsigned long long>(c, 64ull), 4096ull);
     }
-    p.batch = m->opt.batch > 0 ? m->opt.batch : (agg == 2 ? 48 : (replicas > 1 ? 40 : 64));
+    // (forced first interactions add an absorption or scattering to every package: fuller passes then pay)
+    p.batch = m->opt.batch > 0 ? m->opt.batch : (agg == 2 ? (m->opt.ffi ? 56 : 48) : (replicas > 1 ? 40 : 64));
     p.quorum = m->opt.quorum > 0 ? m->opt.quorum : 3;
     L.fp64 = fp64;
     L.agg = agg;
