@@ -540,11 +540,21 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
     // the event pass reloads its record from `ps`; the LDS pad record below
     // the table keeps such a lane's stale reads in bounds.
     unsigned long long fly = 0;    // wave-uniform
+    unsigned long long tneg = 0;   // wave-uniform: lanes with t < 0 (FP32 sweeps)
     int vote = 0;                  // workgroup grouping: the vote word of this pass
     uint32_t sweep_steps = 0;      // moving steps of the current sweep (a sweep ends before 2^32)
     constexpr bool kLoose = std::is_same<R, float>::value;
     auto step = [&]() {
-        const bool inward = (t < (R)0) && (b2 < cur.r2_in);
+        bool inward;
+        if constexpr (kLoose) {
+            // a flight approaches its tangent point (t < 0) exactly while its
+            // crossings so far went inward, so the FP32 kernels carry the mask
+            // of those lanes from step to step instead of comparing t
+            tneg &= __builtin_amdgcn_ballot_w64(b2 < cur.r2_in);
+            inward = __builtin_amdgcn_inverse_ballot_w64(tneg);
+        } else {
+            inward = (t < (R)0) && (b2 < cur.r2_in);
+        }
         const Shell *const pn = inward ? ps - 1 : ps + 1;
         const Shell nx = P<R>::shell(pn);
         KRec nxk{};
@@ -958,6 +968,7 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
             const int live = __popcll(__ballot(st != ST_DONE));
             const int want = batch < live ? batch : (live > 0 ? live : 1);
             fly = __ballot(st == ST_FLY);
+            tneg = __ballot(t < (R)0);
             sweep_steps = 0;
             if constexpr (AGG == 2) {
                 if (live == 0 && !wave_done) {
