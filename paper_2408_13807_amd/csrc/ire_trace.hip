@@ -951,15 +951,15 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
     // counts those without packages left
     const int n_waves = (int)(blockDim.x / kWave);
     bool wave_done = false;
-    constexpr int kStepsPerCheck = AGG == 1 ? 8 : 4;
+    constexpr int kStepsPerCheck = AGG == 1 ? 16 : 8;
     for (;;) {
         // ---- crossing sweep: packages in flight step from boundary to boundary;
         // a package that reaches its interaction parks, and the wave stops stepping
         // when enough of its packages are parked to process their events together.
         // Several steps per check (a step of a parked package changes nothing):
-        // eight with per-wave grouping (measured faster), four with workgroup
-        // grouping, where stopping soon after the quorum matters more, and with
-        // one atomic per lane.  With
+        // sixteen with per-wave grouping, eight with workgroup grouping, where
+        // stopping soon after the quorum matters more, and with one atomic per
+        // lane (measured: fewer checks cost less than the extra steps).  With
         // workgroup grouping every wave waits for the others at the pass, so a
         // wave also stops once `quorum` of the waves that still have packages have
         // ended their sweeps (a wave counts itself only after its own sweep, so
