@@ -157,6 +157,21 @@ __device__ __forceinline__ int count_le_from(const T *t, int n, X x, int pos) {
     return pos;
 }
 
+// count_le_from, also returning the entry the forward scan stopped at
+// (t[pos] > x, infinite past the end), which the caller would otherwise read
+// again.
+template <typename T, typename X>
+__device__ __forceinline__ int count_le_next(const T *t, int n, X x, int pos, X inf, X &next) {
+    while (pos > 0 && (X)t[pos - 1] > x) --pos;
+    X v = pos < n ? (X)t[pos] : inf;
+    while (pos < n && v <= x) {
+        ++pos;
+        v = pos < n ? (X)t[pos] : inf;
+    }
+    next = v;
+    return pos;
+}
+
 // Guide start for a in the G(T) table: bins uniform in log2 a.
 __device__ __forceinline__ int g_guide(const uint16_t *gg, int n_t, float lg0, float scale, float a) {
     const float x = (__log2f(a) - lg0) * scale;
@@ -752,8 +767,9 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
             bool straddle = false;
             if (absorbing) {
                 const R alo = (R)(A_before * invM), ahi = (R)((A_before + E) * invM);
-                row = count_le_from(G, n_t, alo, g_guide(gguide, n_t, g_lg0, g_scale, (float)alo));
-                straddle = row < n_t && G[row] <= ahi;
+                R g_next;
+                row = count_le_next(G, n_t, alo, g_guide(gguide, n_t, g_lg0, g_scale, (float)alo), P<R>::inf(), g_next);
+                straddle = g_next <= ahi;
                 lc.abs++;
             }
             if (absorbing && (kTwoBlocks || straddle || o.reemit_uniform))
