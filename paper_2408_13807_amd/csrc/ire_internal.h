@@ -91,6 +91,10 @@ struct DustD { double kA, kS, inv_kA, inv_kS, g, alb, kext, pad; };
 // and `rk` (the escaping spectrum and the k_A(rho) records) are absent from
 // the batched launch.
 struct LdsLayout { size_t sh, dust, cdf, G, D, guide, sed, rk, agg, total; };
+// Row stride (floats) of the re-emission CDF rows in LDS: odd, so that the
+// lanes of a wave reading the same column of different rows (the first
+// rounds of a four-way search) fall into different banks.
+__host__ __device__ inline int d_stride(int K) { return K | 1; }
 __host__ __device__ inline size_t lds_align16(size_t x) { return (x + 15) & ~(size_t)15; }
 __host__ __device__ inline LdsLayout lds_layout(int n_table, int K, int n_t, bool sed, bool rk, int block) {
     LdsLayout L{};
@@ -99,7 +103,7 @@ __host__ __device__ inline LdsLayout lds_layout(int n_table, int K, int n_t, boo
     L.dust = o;  o = lds_align16(o + (size_t)K * sizeof(DustF));
     L.cdf = o;   o = lds_align16(o + (size_t)2 * K * sizeof(float));
     L.G = o;     o = lds_align16(o + (size_t)n_t * sizeof(float));
-    L.D = o;     o = lds_align16(o + (size_t)n_t * K * sizeof(float));
+    L.D = o;     o = lds_align16(o + (size_t)n_t * d_stride(K) * sizeof(float));
     L.guide = o; o = lds_align16(o + guide_bytes(n_t));
     L.sed = o;   o = lds_align16(o + (sed ? (size_t)4 * K * sizeof(double) : 0));
     L.rk = o;    o = lds_align16(o + (rk ? (size_t)(n_table + kPadBelow) * 2 * sizeof(float) : 0));

@@ -466,7 +466,7 @@ struct MethodOpts {
 template <typename R, int AGG, int WT>
 __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodOpts &o,
                                             const typename P<R>::Dust *dust, const R *cdf,
-                                            const R *G, const R *D, int K, int n_t,
+                                            const R *G, const R *D, int K, int n_t, int ldD,
                                             const unsigned char *guide, float g_lg0, float g_scale,
                                             const typename P<R>::KRec *rk,
                                             unsigned long long *cursor, unsigned long long chunk,
@@ -782,7 +782,7 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
                 if (row > n_t - 1) { row = n_t - 1; lc.reabove++; }
             }
             if (launching || absorbing) {
-                const R *tab = launching ? cdf + src * K : D + (size_t)row * K;
+                const R *tab = launching ? cdf + src * K : D + (size_t)row * ldD;
                 const R u = P<R>::uni(launching ? r1.x : r1.y);
                 k = min(count_le4(tab, K, u), K - 1);
             }
@@ -1133,8 +1133,11 @@ __global__ __launch_bounds__(kBlockFP32) void ire_trace_f32(TraceParams p) {
     for (int j = threadIdx.x; j < K; j += blockDim.x) s_dust[j] = p.dustf[j];
     for (int j = threadIdx.x; j < 2 * K; j += blockDim.x) s_cdf[j] = p.cdff[j];
     for (int j = threadIdx.x; j < n_t; j += blockDim.x) s_G[j] = p.Gf[j];
-    const int nd = n_t * K;
-    for (int j = threadIdx.x; j < nd; j += blockDim.x) s_D[j] = p.Df[j];
+    const int nd = n_t * K, ldD = d_stride(K);
+    for (int j = threadIdx.x; j < nd; j += blockDim.x) {
+        const int r = j / K;
+        s_D[r * ldD + (j - r * K)] = p.Df[j];
+    }
     const int ng = (int)(guide_bytes(n_t) / 4);
     for (int j = threadIdx.x; j < ng; j += blockDim.x) s_guide[j] = reinterpret_cast<const uint32_t *>(p.guide)[j];
     double *s_sed = reinterpret_cast<double *>(smem + L.sed);
@@ -1150,7 +1153,8 @@ __global__ __launch_bounds__(kBlockFP32) void ire_trace_f32(TraceParams p) {
     single_model<float>(p, s_sh, mc, o);
     const long long gtid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     LaneCounters lc;
-    trace_model<float, AGG, WT>(mc, o, s_dust, s_cdf, s_G, s_D, K, n_t, reinterpret_cast<const unsigned char *>(s_guide),
+    trace_model<float, AGG, WT>(mc, o, s_dust, s_cdf, s_G, s_D, K, n_t, d_stride(K),
+                                reinterpret_cast<const unsigned char *>(s_guide),
                                 p.g_lg0, p.g_scale, s_rk, &p.stats->cursor, p.chunk,
                                  p.max_lanes > 0 && gtid >= p.max_lanes, lc, s_sed, s_agg + threadIdx.x / kWave,
                                  reinterpret_cast<WgScratch *>(s_agg));
@@ -1170,7 +1174,7 @@ __global__ __launch_bounds__(256) void ire_trace_f64(TraceParams p) {
     single_model<double>(p, p.shd, mc, o);
     const long long gtid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     LaneCounters lc;
-    trace_model<double, AGG, WT>(mc, o, p.dustd, p.cdfd, p.Gd, p.Dd, p.K, p.n_t, p.guide, p.g_lg0, p.g_scale,
+    trace_model<double, AGG, WT>(mc, o, p.dustd, p.cdfd, p.Gd, p.Dd, p.K, p.n_t, p.K, p.guide, p.g_lg0, p.g_scale,
                                  p.rkd, &p.stats->cursor, p.chunk, p.max_lanes > 0 && gtid >= p.max_lanes, lc, s_sed,
                                  reinterpret_cast<AggScratch *>(s_sed + 4 * p.K) + threadIdx.x / kWave,
                                  reinterpret_cast<WgScratch *>(s_sed + 4 * p.K));
@@ -1246,8 +1250,11 @@ __global__ __launch_bounds__(kBlockFP32) void ire_trace_batch(BatchParams p) {
     for (int j = threadIdx.x; j < K; j += blockDim.x) s_dust[j] = p.dustf[j];
     for (int j = threadIdx.x; j < 2 * K; j += blockDim.x) s_cdf[j] = p.cdff[j];
     for (int j = threadIdx.x; j < n_t; j += blockDim.x) s_G[j] = p.Gf[j];
-    const int nd = n_t * K;
-    for (int j = threadIdx.x; j < nd; j += blockDim.x) s_D[j] = p.Df[j];
+    const int nd = n_t * K, ldD = d_stride(K);
+    for (int j = threadIdx.x; j < nd; j += blockDim.x) {
+        const int r = j / K;
+        s_D[r * ldD + (j - r * K)] = p.Df[j];
+    }
     const int ng = (int)(guide_bytes(n_t) / 4);
     for (int j = threadIdx.x; j < ng; j += blockDim.x) s_guide[j] = reinterpret_cast<const uint32_t *>(p.guide)[j];
     AggScratch *s_agg = reinterpret_cast<AggScratch *>(smem + L.agg);
@@ -1297,7 +1304,7 @@ __global__ __launch_bounds__(kBlockFP32) void ire_trace_batch(BatchParams p) {
         mc.pid0[0] = item.first;
         mc.pid0[1] = item.first;
         mc.seed = bm.seed;
-        trace_model<float, AGG, WT>(mc, o, s_dust, s_cdf, s_G, s_D, K, n_t,
+        trace_model<float, AGG, WT>(mc, o, s_dust, s_cdf, s_G, s_D, K, n_t, d_stride(K),
                                     reinterpret_cast<const unsigned char *>(s_guide), p.g_lg0, p.g_scale, s_rk,
                                     &s_cursor,
                                      64ull, false, lc, nullptr, s_agg + threadIdx.x / kWave, nullptr);

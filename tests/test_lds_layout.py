@@ -28,7 +28,7 @@ int main() {
         const LdsLayout L = lds_layout(n_table, K, nt, sed, rk, 1024);
         const size_t off[10] = {L.sh, L.dust, L.cdf, L.G, L.D, L.guide, L.sed, L.rk, L.agg, L.total};
         const size_t need[9] = {(size_t)(n_table + kPadBelow) * sizeof(ShellF), (size_t)K * sizeof(DustF),
-                                (size_t)2 * K * 4, (size_t)nt * 4, (size_t)nt * K * 4, guide_bytes(nt),
+                                (size_t)2 * K * 4, (size_t)nt * 4, (size_t)nt * (K | 1) * 4, guide_bytes(nt),
                                 sed ? (size_t)4 * K * 8 : 0, rk ? (size_t)(n_table + kPadBelow) * 8 : 0,
                                 agg_lds_bytes(1024)};
         for (int j = 0; j < 10; ++j) {
