@@ -89,7 +89,7 @@ typedef struct ire_options {
                              crossing sweeps at `batch` parked lanes, the others end theirs early and the
                              workgroup runs its event pass; with `quorum` or fewer waves left with packages
                              each wave sweeps to its own batch (1..16; 16: every wave always does; 0 = default:
-                             3); changes speed, not the distribution of results */
+                             2, 3 with ffi); changes speed, not the distribution of results */
 } ire_options;
 
 typedef struct ire_stats {

@@ -166,7 +166,7 @@ struct TraceLaunch {
 int trace_launch_setup(ire_model *m, int replicas, uint64_t n_ext, uint64_t n_ps, TraceLaunch &L) {
     // schedule: with one running total per shell, per-lane or per-wave atomics on the few addresses bound
     // the launch, and grouping the absorptions of the whole workgroup (its waves pass together, at 48 parked
-    // lanes, or once 3 waves are there) makes the fewest; with accumulator groups the launch is
+    // lanes, or once 2 waves are there) makes the fewest; with accumulator groups the launch is
     // instruction-bound, and per-wave grouping at 40 parked lanes is the better balance
     const int agg = m->opt.aggregate >= 0 ? m->opt.aggregate : (replicas > 1 ? 1 : 2);
     if (agg == 2 && m->rho.size() >= (1u << 22))
@@ -220,9 +220,10 @@ int trace_launch_setup(ire_model *m, int replicas, uint64_t n_ext, uint64_t n_ps
         unsigned long long c = (n_ext + n_ps) / (waves * 64ull);
         p.chunk = std::min<unsigned long long>(std::max<unsigned long long>(c, 64ull), 4096ull);
     }
-    // (forced first interactions add an absorption or scattering to every package: fuller passes then pay)
+    // (forced first interactions add an absorption or scattering to every package: fuller passes, more
+    // parked lanes and a larger quorum, then pay)
     p.batch = m->opt.batch > 0 ? m->opt.batch : (agg == 2 ? (m->opt.ffi ? 56 : 48) : (replicas > 1 ? 40 : 64));
-    p.quorum = m->opt.quorum > 0 ? m->opt.quorum : 3;
+    p.quorum = m->opt.quorum > 0 ? m->opt.quorum : (m->opt.ffi ? 3 : 2);
     L.fp64 = fp64;
     L.agg = agg;
     L.grid = grid;
