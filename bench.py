@@ -26,10 +26,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# VALU instructions one lane executes per event on the FP32 tracer's paths
-# (least-squares fit of SQ_INSTS_VALU over one-lane runs of six clouds;
-# profiles/valu_fit_one_lane_clouds.md holds the fit and its command).
-VALU_PER_EVENT = {"cross": 18.95, "launch": 277.61, "scat": 280.96, "abs": 309.27}
+# VALU instructions one lane executes per event on the FP32 tracer's paths:
+# a crossing is one sweep step, and a launch, scattering or absorption is its
+# own path plus the step that found it (least-squares fit of SQ_INSTS_VALU
+# over one-lane runs of six clouds, with the sweeps' steps fitted apart from
+# the events so that steps that move nothing after the lane parked are not
+# counted as work; profiles/valu_fit_one_lane_clouds.md holds the fit and its
+# command).
+VALU_PER_EVENT = {"cross": 17.15, "launch": 236.77, "scat": 240.30, "abs": 266.73}
 
 # HBM bytes per tracer launch from FETCH_SIZE and WRITE_SIZE, scaled by a
 # plain 1 GiB copy (profiles/ire_trace_f32_ext101_tauV10_1e8.md); valid for

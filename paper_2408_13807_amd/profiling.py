@@ -33,6 +33,7 @@ import sys
 import numpy as np
 
 EVENTS = ("n_cross", "n_launch", "n_scat", "n_abs")
+FLIGHT_EVENTS = ("n_launch", "n_scat", "n_abs")
 
 
 def valu_cases() -> list[dict]:
@@ -51,7 +52,7 @@ def valu_cases() -> list[dict]:
         # and the workgroup's idle waves run no event passes beside it (their
         # instructions are no work of the package)
         r = ire.run_model(m, seed=1, max_lanes=1, aggregate=0, **kw)
-        out.append(dict(name=name, **{k: r["stats"][k] for k in EVENTS}))
+        out.append(dict(name=name, **{k: r["stats"][k] for k in EVENTS + ("n_step_slots",)}))
     return out
 
 
@@ -68,14 +69,24 @@ def _counters(db: str) -> list[dict]:
 
 
 def valu_fit(db: str, cases: list[dict]) -> dict:
+    """Least squares SQ_INSTS_VALU = c0 + c_step * steps + sum_e c_e n_e over
+    the one-lane runs, steps = the lane's crossing-sweep steps (n_step_slots /
+    64).  A sweep runs several steps per check, so after its lane parks a
+    sweep may run a few steps that move nothing: fitting the steps apart from
+    the events keeps those out of the events' costs.  The algorithmic work of
+    an event is then its own path plus the one step that found it (every event
+    but an escape ends a flight), and of a crossing one step."""
     disp = [c for c in _counters(db) if "ire_trace" in c["kernel"]]
     if len(disp) != len(cases):
         raise ValueError(f"{len(disp)} tracer dispatches but {len(cases)} cases")
-    X = np.array([[1.0] + [c[e] for e in EVENTS] for c in cases])
+    X = np.array([[1.0, c["n_step_slots"] / 64.0] + [c[e] for e in FLIGHT_EVENTS] for c in cases])
     y = np.array([d["SQ_INSTS_VALU"] for d in disp])
     coef = np.linalg.lstsq(X, y, rcond=None)[0]
     resid = (X @ coef - y) / y
-    return {"per_lane_valu": {e[2:]: float(c) for e, c in zip(EVENTS, coef[1:])},
+    c_step = float(coef[1])
+    return {"per_lane_valu": {"step": c_step, **{e[2:]: float(c) for e, c in zip(FLIGHT_EVENTS, coef[2:])}},
+            "algorithmic_per_event": {"cross": c_step,
+                                      **{e[2:]: float(c) + c_step for e, c in zip(FLIGHT_EVENTS, coef[2:])}},
             "constant": float(coef[0]), "max_rel_residual": float(np.max(np.abs(resid))),
             "cases": [dict(c, SQ_INSTS_VALU=d["SQ_INSTS_VALU"]) for c, d in zip(cases, disp)]}
 
