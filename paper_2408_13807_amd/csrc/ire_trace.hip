@@ -574,6 +574,9 @@ __device__ __forceinline__ void trace_model(const ModelCtx<R> &mc, const MethodO
         const Shell nx = P<R>::shell(pn);
         KRec nxk{};
         if constexpr (KRHO) nxk = rk[pn - sh];
+        // the FP32 kernels issue the record's load before the step's arithmetic
+        // (the scheduler would otherwise place it after the square root)
+        if constexpr (kLoose) __builtin_amdgcn_sched_barrier(0);
         const R arg = (inward ? cur.r2_in : cur.r2_out) - b2;
         // arg >= 0 but for rounding at a tangent point or on a boundary: the FP32
         // kernels take |arg| (a free source modifier of the square root, within
