@@ -38,7 +38,7 @@ VALU_PER_EVENT = {"cross": 17.15, "launch": 236.77, "scat": 240.30, "abs": 266.7
 # HBM bytes per tracer launch from FETCH_SIZE and WRITE_SIZE, scaled by a
 # plain 1 GiB copy (profiles/ire_trace_f32_ext101_tauV10_1e8.md); valid for
 # the tracer as profiled and set to None whenever the kernel changes.
-TRAFFIC_BYTES = {"ext101_tauV10_1e8": 6.078e8}
+TRAFFIC_BYTES = {"ext101_tauV10_1e8": 6.068e8}
 
 # MI355X VALU lane-instruction issue peak: the published FP32 vector rate of
 # 157.3 TFLOP/s is 78.6e12 FMAs per second, i.e. 256 CUs x 4 SIMDs x 32 lanes
