@@ -18,10 +18,11 @@ constexpr int kIn = 32;        // inputs padded to the MFMA k granularity
 //   off_b:    depth*kWidth          hidden biases
 //   off_wout: kWidth                output weights
 //   off_bout: 1                     output bias
-// The BF16 weights W share the weight part of that layout; WT holds each block transposed.
+// The BF16 weights W share the weight part of that layout; WT holds each block transposed,
+// and Wf each block in the order in which inference reads its MFMA fragments (frag_index).
 struct NetView {
     int members, depth;
-    __bf16 *W, *WT;
+    __bf16 *W, *WT, *Wf;
     float *b, *wout, *bout;
     size_t w_stride, b_stride, p_stride;
     size_t off_b, off_wout, off_bout;
@@ -55,6 +56,14 @@ struct TrainView {
     float *grad, *master, *adam_m, *adam_v;  // [M][p_stride]
 };
 
+// Position in a Wf block of the weight of output o and input i (K inputs): the block
+// holds, for each 32-output group and each k step of 16 inputs, one MFMA A fragment
+// of 64 lanes x 8 inputs (lane = 32 * ((i >> 3) & 1) + o % 32, input i % 8 in the
+// lane's 8), so that a wave reads a fragment as 1 KB of contiguous memory.
+__host__ __device__ inline size_t frag_index(size_t o, size_t i, size_t K) {
+    return ((((o >> 5) * (K >> 4) + (i >> 4)) * 64 + ((i >> 3) & 1) * 32 + (o & 31)) << 3) + (i & 7);
+}
+
 // Write one master parameter (member m, flat index q) into the BF16/FP32 copies the kernels read.
 __device__ __forceinline__ void scatter_param(const NetView &v, int m, size_t q, float p) {
     if (q < v.off_b) {
@@ -70,6 +79,7 @@ __device__ __forceinline__ void scatter_param(const NetView &v, int m, size_t q,
         const size_t e = q - blk;
         const size_t o = e / K, i = e % K;
         v.WT[(size_t)m * v.w_stride + blk + i * kWidth + o] = (__bf16)p;
+        v.Wf[(size_t)m * v.w_stride + blk + frag_index(o, i, K)] = (__bf16)p;
     } else if (q < v.off_wout) {
         v.b[(size_t)m * v.b_stride + (q - v.off_b)] = p;
     } else if (q < v.off_bout) {

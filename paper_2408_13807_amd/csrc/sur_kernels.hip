@@ -126,56 +126,107 @@ __device__ __forceinline__ float out_row(const __bf16 *h, const float *wout, flo
 // ---------------------------------------------------------------------------
 // Inference: every member on every row; mean log10 T and relative spread of T.
 
-// Row inputs for prediction: a row-major [n][kFeatures] matrix ...
+// Inference keeps every activation, and the inputs, multiplied by
+// kActScale = -log2(e): the pre-activations are then -log2(e) z, the argument
+// of the exp2 in SiLU(z) = z / (1 + e^-z), and the scaled SiLU is t / (1 +
+// 2^t) for t = -log2(e) z.  The weights are unchanged; the biases are scaled
+// as they are loaded and the output layer divides by kActScale.
+constexpr float kActScale = -1.44269504088896341f;
+constexpr float kInvActScale = -0.693147180559945309f;
+
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    const bf16x2 v = __builtin_convertvector(f32x2{a, b}, bf16x2);
+    return __builtin_bit_cast(uint32_t, v);
+}
+
+// One row of the inference input tile: the network's inputs from the six
+// features (normalised; the derived log-radius input), times kActScale, as
+// BF16, zero padded to kIn; rows at or beyond n are zero.
+__device__ __forceinline__ void stage_row(const float (&f)[kFeatures], bool valid, const NetView &v, __bf16 *xrow) {
+    float x[kNetInputs];
+#pragma unroll
+    for (int c = 0; c < kFeatures; ++c) x[c] = (f[c] - v.x_mean[c]) * v.x_inv_std[c];
+    x[kLogRadius] = log_radius_input(f[kFeatures - 1]);
+    uint32_t p[kIn / 2];
+#pragma unroll
+    for (int c = 0; c < kIn / 2; ++c) {
+        const float a = 2 * c < kNetInputs && valid ? x[2 * c] * kActScale : 0.0f;
+        const float b = 2 * c + 1 < kNetInputs && valid ? x[2 * c + 1] * kActScale : 0.0f;
+        p[c] = pack_bf16x2(a, b);
+    }
+#pragma unroll
+    for (int c = 0; c < kIn / 8; ++c)
+        *reinterpret_cast<uint4 *>(xrow + 8 * c) = uint4{p[4 * c], p[4 * c + 1], p[4 * c + 2], p[4 * c + 3]};
+}
+
+// Row inputs for prediction: a row-major [n][kFeatures] matrix (one thread
+// per row, its loads in flight together) ...
 struct RowInputs {
     const float *X;
     __device__ __forceinline__ void operator()(int64_t n, int64_t row0, const NetView &v, __bf16 *xs) const {
-        load_inputs(X, n, row0, v, xs);
+        if (threadIdx.x < kR) {
+            const int64_t row = row0 + threadIdx.x;
+            const bool valid = row < n;
+            float f[kFeatures];
+#pragma unroll
+            for (int c = 0; c < kFeatures; ++c) f[c] = valid ? X[row * kFeatures + c] : 0.0f;
+            stage_row(f, valid, v, xs + threadIdx.x * kLdX);
+        }
     }
 };
 
 // ... or whole models: the cloud parameters once per model (feature columns
 // 0..4) and the shells' relative mid-radii (column 5) from a radius table in
-// which models with the same shell grid may share their values.
+// which models with the same shell grid may share their values.  The first
+// wave finds the model holding row0 by a 64-way search and stages the next 64
+// model boundaries in LDS, where each row finds its model.
 struct ModelInputs {
     ModelRows q;
     __device__ __forceinline__ void operator()(int64_t n, int64_t row0, const NetView &v, __bf16 *xs) const {
-        __shared__ int64_t s_model[kR];
+        __shared__ int64_t s_bnd[64];
         __shared__ int64_t s_first;
-        if (threadIdx.x == 0) {
-            // the model holding row0: last m with row_off[m] <= row0
+        const int lane = threadIdx.x & 63;
+        if (threadIdx.x < 64) {
+            // last m with row_off[m] <= row0 (row_off[0] = 0 <= row0); it lies in [lo, hi]
             int64_t lo = 0, hi = q.n_models - 1;
-            while (lo < hi) {
-                const int64_t mid = (lo + hi + 1) >> 1;
-                if (q.row_off[mid] <= row0) lo = mid; else hi = mid - 1;
+            while (hi > lo) {
+                const int64_t step = (hi - lo + 63) / 64;
+                const int64_t c = lo + (lane + 1) * step;
+                const bool ok = c <= hi && q.row_off[c] <= row0;
+                lo += step * __popcll(__ballot(ok));
+                hi = min(hi, lo + step - 1);
             }
-            s_first = lo;
+            const int64_t b = lo + 1 + lane;
+            s_bnd[lane] = b < q.n_models ? q.row_off[b] : INT64_MAX;
+            if (lane == 0) s_first = lo;
         }
         __syncthreads();
         if (threadIdx.x < kR) {
             const int64_t row = row0 + threadIdx.x;
+            const bool valid = row < n;
             int64_t m = s_first;
-            if (row < n)
-                while (m + 1 < q.n_models && q.row_off[m + 1] <= row) ++m;
-            s_model[threadIdx.x] = m;
-        }
-        __syncthreads();
-        for (int j = threadIdx.x; j < kR * kIn; j += blockDim.x) {
-            const int r = j / kIn, c = j % kIn;
-            const int64_t row = row0 + r;
-            float x = 0.0f;
-            if ((c < kFeatures || c == kLogRadius) && row < n) {
-                const int64_t m = s_model[r];
-                if (c < kFeatures - 1) {
-                    x = (q.model_x[m * (kFeatures - 1) + c] - v.x_mean[c]) * v.x_inv_std[c];
+            if (valid) {
+                // boundaries s_bnd[i] = row_off[s_first + 1 + i] <= row, counted by bisection
+                int c = 0;
+                if (s_bnd[63] <= row) {
+                    c = 64;
                 } else {
-                    const int64_t k = q.radius_off[m] + (row - q.row_off[m]);
-                    const float rr = (k >= 0 && k < q.n_radius) ? q.radius[k] : 0.0f;
-                    x = c == kLogRadius ? log_radius_input(rr)
-                                        : (rr - v.x_mean[kFeatures - 1]) * v.x_inv_std[kFeatures - 1];
+#pragma unroll
+                    for (int step = 32; step > 0; step >>= 1)
+                        if (s_bnd[c + step - 1] <= row) c += step;
                 }
+                m += c;
+                if (c == 64)        // a tile over more than 64 models
+                    while (m + 1 < q.n_models && q.row_off[m + 1] <= row) ++m;
             }
-            xs[r * kLdX + c] = (__bf16)x;
+            float f[kFeatures];
+            const int64_t k = valid ? q.radius_off[m] + (row - q.row_off[m]) : -1;
+#pragma unroll
+            for (int c = 0; c < kFeatures - 1; ++c) f[c] = valid ? q.model_x[m * (kFeatures - 1) + c] : 0.0f;
+            f[kFeatures - 1] = (k >= 0 && k < q.n_radius) ? q.radius[k] : 0.0f;
+            stage_row(f, valid, v, xs + threadIdx.x * kLdX);
         }
     }
 };
@@ -185,33 +236,26 @@ struct ModelInputs {
 // overwrites in place (the layer's products are complete in registers before
 // the buffer is rewritten), so a workgroup takes ~80 KB of LDS and two run on
 // a CU.  Wave w computes output features [64w, 64w + 64) of every layer:
-// accumulators start at the bias, the weight fragments of the next kAhead k
-// steps are in flight in a register ring and the activation fragments of the
-// next step are requested before the current step's eight MFMAs; SiLU costs
-// one exp2 and one reciprocal, and pairs of results are converted to BF16
-// together.  The output layer w_out . h is folded into the last hidden
-// layer's epilogue: each lane sums its 32 features of 4 rows, the two
-// half-waves and then the 4 waves are added, and the thread of each row
-// accumulates the moments of T over the members.
+// accumulators start at the (scaled) bias; the weights are read in fragment
+// order (frag_index), one contiguous 1 KB load per fragment, and the fragments
+// of the next kAhead k steps are in flight in a register ring; the activation
+// fragments of the next step are requested right after the current step's
+// first MFMA (the order within a step is pinned: left to itself the compiler
+// moves the loads next to their use).  SiLU costs one exp2 and one
+// reciprocal, and pairs of results are converted to BF16 together.  The output
+// layer w_out . h is folded into the last hidden layer's epilogue (FP32
+// activations): each lane sums its 32 features of 4 rows, the two half-waves
+// and then the 4 waves are added, and the thread of each row accumulates the
+// moments of T over the members.
 constexpr int kPredictWaves = kThreads / 64;
 
-__device__ __forceinline__ float silu_fast(float z) {
-    // z / (1 + e^-z) with the hardware exp2 and reciprocal
-    return z * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.44269504088896341f * z));
+// kActScale * SiLU(z) from t = kActScale * z, with the hardware exp2 and reciprocal
+__device__ __forceinline__ float silu_scaled(float t) {
+    return t * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(t));
 }
 
-__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
-    typedef float f32x2 __attribute__((ext_vector_type(2)));
-    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-    const bf16x2 v = __builtin_convertvector(f32x2{a, b}, bf16x2);
-    return __builtin_bit_cast(uint32_t, v);
-}
-
-__device__ __forceinline__ float bf16_lo(uint32_t u) { return __builtin_bit_cast(float, u << 16); }
-__device__ __forceinline__ float bf16_hi(uint32_t u) { return __builtin_bit_cast(float, u & 0xFFFF0000u); }
-
-// acc[a][b] = bias + W . hin^T for this wave's 64 output features and the kR
-// rows; lane l holds in entry r of acc[a][b] feature 64 w + 32 a + 8 (r >> 2)
+// acc[a][b] = kActScale (bias + W . h^T) for this wave's 64 output features
+// and the kR rows, from W in fragment order and hin = kActScale h; lane l holds in entry r of acc[a][b] feature 64 w + 32 a + 8 (r >> 2)
 // + 4 (l >> 5) + (r & 3) of row 32 b + (l & 31).
 template <int K>
 __device__ __forceinline__ void predict_layer(const __bf16 *W, const float *bias, const __bf16 *hin, int ldin,
@@ -226,23 +270,25 @@ __device__ __forceinline__ void predict_layer(const __bf16 *W, const float *bias
             const float4 bv = *reinterpret_cast<const float4 *>(bb + 8 * g);
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                acc[a][b][4 * g + 0] = bv.x;
-                acc[a][b][4 * g + 1] = bv.y;
-                acc[a][b][4 * g + 2] = bv.z;
-                acc[a][b][4 * g + 3] = bv.w;
+                acc[a][b][4 * g + 0] = bv.x * kActScale;
+                acc[a][b][4 * g + 1] = bv.y * kActScale;
+                acc[a][b][4 * g + 2] = bv.z * kActScale;
+                acc[a][b][4 * g + 3] = bv.w * kActScale;
             }
         }
     }
-    const __bf16 *wrow0 = W + (size_t)(wave * 64 + l32) * K + 8 * half;
-    const __bf16 *wrow1 = wrow0 + (size_t)32 * K;
-    const __bf16 *hrow = hin + l32 * ldin + 8 * half;
     constexpr int kSteps = K / 16;
+    // fragment-ordered weights: the fragment of 32-output group q and k step st is
+    // 512 contiguous values, this lane's 8 at offset 8 * lane
+    const __bf16 *wrow0 = W + ((size_t)(wave * 2) * kSteps * 64 + lane) * 8;
+    const __bf16 *wrow1 = wrow0 + (size_t)kSteps * 512;
+    const __bf16 *hrow = hin + l32 * ldin + 8 * half;
     constexpr int kAhead = kSteps < 4 ? kSteps : 4;
     bf16x8 wa[kAhead][2], hb[2][4];
 #pragma unroll
     for (int s = 0; s < kAhead; ++s) {
-        wa[s][0] = *reinterpret_cast<const bf16x8 *>(wrow0 + 16 * s);
-        wa[s][1] = *reinterpret_cast<const bf16x8 *>(wrow1 + 16 * s);
+        wa[s][0] = *reinterpret_cast<const bf16x8 *>(wrow0 + 512 * s);
+        wa[s][1] = *reinterpret_cast<const bf16x8 *>(wrow1 + 512 * s);
     }
 #pragma unroll
     for (int b = 0; b < 4; ++b) hb[0][b] = *reinterpret_cast<const bf16x8 *>(hrow + b * 32 * ldin);
@@ -251,8 +297,8 @@ __device__ __forceinline__ void predict_layer(const __bf16 *W, const float *bias
         const int k = 16 * st;
         const bf16x8 c0 = wa[st % kAhead][0], c1 = wa[st % kAhead][1];
         if (st + kAhead < kSteps) {
-            wa[st % kAhead][0] = *reinterpret_cast<const bf16x8 *>(wrow0 + k + 16 * kAhead);
-            wa[st % kAhead][1] = *reinterpret_cast<const bf16x8 *>(wrow1 + k + 16 * kAhead);
+            wa[st % kAhead][0] = *reinterpret_cast<const bf16x8 *>(wrow0 + 512 * (st + kAhead));
+            wa[st % kAhead][1] = *reinterpret_cast<const bf16x8 *>(wrow1 + 512 * (st + kAhead));
         }
         if (st + 1 < kSteps) {
 #pragma unroll
@@ -264,15 +310,23 @@ __device__ __forceinline__ void predict_layer(const __bf16 *W, const float *bias
             acc[0][b] = mfma(c0, hb[st & 1][b], acc[0][b]);
             acc[1][b] = mfma(c1, hb[st & 1][b], acc[1][b]);
         }
+        // one MFMA, the next step's 4 LDS reads, the 2 weight loads, the other 7 MFMAs
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+        __builtin_amdgcn_sched_group_barrier(0x020, 2, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 7, 0);
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
-// Epilogue of a hidden layer: SiLU of the accumulators, rounded to BF16.
-// Hidden layers store the values into the tile buffer; the last hidden layer
-// instead folds the output layer in: this wave's part of w_out . h for the 4
-// rows b * 32 + l32, summed over the two half-waves into ysum[wave][row].
-__device__ __forceinline__ void predict_epilogue(const f32x16 (&acc)[2][4], __bf16 *hout, bool last,
-                                                 const float *wout, float *ysum) {
+// Epilogue of a hidden layer: the scaled SiLU of the accumulators.  Hidden
+// layers store the values, rounded to BF16, into the tile buffer; the last
+// hidden layer instead folds the output layer in (FP32 values): this wave's
+// part of w_out . (kActScale h) for the 4 rows b * 32 + l32, summed over the
+// two half-waves into ysum[wave][row].
+template <bool kLast>
+__device__ __forceinline__ void predict_epilogue(const f32x16 (&acc)[2][4], __bf16 *hout, const float *wout,
+                                                 float *ysum) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int half = lane >> 5, l32 = lane & 31;
     float y[4] = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -282,20 +336,21 @@ __device__ __forceinline__ void predict_epilogue(const f32x16 (&acc)[2][4], __bf
         for (int g = 0; g < 4; ++g) {
             const int o = wave * 64 + a * 32 + 8 * g + 4 * half;
             float4 w = float4{0.0f, 0.0f, 0.0f, 0.0f};
-            if (last) w = *reinterpret_cast<const float4 *>(wout + o);
+            if constexpr (kLast) w = *reinterpret_cast<const float4 *>(wout + o);
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                const uint32_t lo = pack_bf16x2(silu_fast(acc[a][b][4 * g]), silu_fast(acc[a][b][4 * g + 1]));
-                const uint32_t hi = pack_bf16x2(silu_fast(acc[a][b][4 * g + 2]), silu_fast(acc[a][b][4 * g + 3]));
-                if (last)
-                    y[b] += w.x * bf16_lo(lo) + w.y * bf16_hi(lo) + w.z * bf16_lo(hi) + w.w * bf16_hi(hi);
+                const float s0 = silu_scaled(acc[a][b][4 * g]), s1 = silu_scaled(acc[a][b][4 * g + 1]);
+                const float s2 = silu_scaled(acc[a][b][4 * g + 2]), s3 = silu_scaled(acc[a][b][4 * g + 3]);
+                if constexpr (kLast)
+                    y[b] += w.x * s0 + w.y * s1 + w.z * s2 + w.w * s3;
                 else
-                    *reinterpret_cast<uint2 *>(hout + (b * 32 + l32) * kLd + o) = uint2{lo, hi};
-                // keep the scheduler from gathering every transcendental of the tile at once
-                __builtin_amdgcn_sched_barrier(0);
+                    *reinterpret_cast<uint2 *>(hout + (b * 32 + l32) * kLd + o) =
+                        uint2{pack_bf16x2(s0, s1), pack_bf16x2(s2, s3)};
             }
+            // keep the scheduler from gathering every transcendental of the tile at once
+            __builtin_amdgcn_sched_barrier(0);
         }
-    if (last) {
+    if constexpr (kLast) {
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             y[b] += __shfl_xor(y[b], 32, 64);
@@ -316,7 +371,7 @@ __global__ __launch_bounds__(kThreads, 2) void sur_predict_kernel(NetView v, Inp
     float s_log = 0.0f, s_T = 0.0f, s_T2 = 0.0f;
     f32x16 acc[2][4];
     for (int m = 0; m < v.members; ++m) {
-        const __bf16 *W = v.W + (size_t)m * v.w_stride;
+        const __bf16 *W = v.Wf + (size_t)m * v.w_stride;
         const float *b = v.b + (size_t)m * v.b_stride;
         __syncthreads();                    // inputs staged / the previous member's sums read
         for (int l = 0; l < v.depth; ++l) {
@@ -328,13 +383,17 @@ __global__ __launch_bounds__(kThreads, 2) void sur_predict_kernel(NetView v, Inp
                 if (l + 1 < v.depth) __syncthreads();   // every wave has read layer l - 1: overwrite in place
             }
             // (layer 0 reads the input tile, and the previous member's last layer only read h)
-            predict_epilogue(acc, h, l + 1 == v.depth, v.wout + (size_t)m * kW, ysum);
+            if (l + 1 == v.depth)
+                predict_epilogue<true>(acc, h, v.wout + (size_t)m * kW, ysum);
+            else
+                predict_epilogue<false>(acc, h, v.wout + (size_t)m * kW, ysum);
         }
         __syncthreads();                    // the waves' output sums
         if (threadIdx.x < kR) {
-            float y = v.bout[m];
+            float y = 0.0f;
 #pragma unroll
             for (int w = 0; w < kPredictWaves; ++w) y += ysum[w * kR + threadIdx.x];
+            y = y * kInvActScale + v.bout[m];
             const float lt = y * v.y_std + v.y_mean;       // log10 T of this member
             const float T = exp10f(lt);
             s_log += lt;

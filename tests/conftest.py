@@ -21,7 +21,10 @@ def orc():
 
 
 def pytest_terminal_summary(terminalreporter):
+    # the parity comparisons' z-score distribution tests (named; the unnamed ones are
+    # the statistics' own tests on synthetic draws, some shifted on purpose)
     mc = sys.modules.get("mc_stats")
-    if mc is not None and mc.KS_PVALUES:
-        name, p = min(mc.KS_PVALUES, key=lambda x: x[1])
-        terminalreporter.write_line(f"z-score distribution tests: {len(mc.KS_PVALUES)}, smallest p = {p:.3g} ({name})")
+    named = [x for x in mc.KS_PVALUES if x[0]] if mc is not None else []
+    if named:
+        name, p = min(named, key=lambda x: x[1])
+        terminalreporter.write_line(f"z-score distribution tests: {len(named)}, smallest p = {p:.3g} ({name})")
