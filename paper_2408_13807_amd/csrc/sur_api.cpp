@@ -25,7 +25,7 @@ struct sur_net {
     float x_mean[sur::kFeatures] = {0}, x_std[sur::kFeatures] = {1, 1, 1, 1, 1, 1};
     float y_mean = 0.0f, y_std = 1.0f;
     bool norm_set = false;
-    DevBuf<__bf16> W, WT, Wf;
+    DevBuf<__bf16> WT, Wf;
     DevBuf<float> b, wout, bout, master, grad, adam_m, adam_v;
     // training workspace
     int64_t cap_batch = 0;
@@ -49,7 +49,6 @@ struct sur_net {
         sur::NetView v{};
         v.members = members;
         v.depth = depth;
-        v.W = W.p;
         v.WT = WT.p;
         v.Wf = Wf.p;
         v.b = b.p;
@@ -168,8 +167,7 @@ int sur_create(int hip_device, int32_t members, int32_t width, int32_t depth, ui
     s->p_stride = s->off_bout + 1;
     const size_t M = members;
     if (hipSetDevice(hip_device) != hipSuccess || hipStreamCreate(&s->cap) != hipSuccess ||
-        s->W.ensure(M * s->w_stride) != hipSuccess || s->WT.ensure(M * s->w_stride) != hipSuccess ||
-        s->Wf.ensure(M * s->w_stride) != hipSuccess ||
+        s->WT.ensure(M * s->w_stride) != hipSuccess || s->Wf.ensure(M * s->w_stride) != hipSuccess ||
         s->b.ensure(M * s->b_stride) != hipSuccess || s->wout.ensure(M * W) != hipSuccess ||
         s->bout.ensure(M) != hipSuccess || s->master.ensure(M * s->p_stride) != hipSuccess ||
         s->grad.ensure(M * s->p_stride) != hipSuccess || s->adam_m.ensure(M * s->p_stride) != hipSuccess ||
@@ -208,7 +206,7 @@ void sur_destroy(sur_net *s) {
     if (!s) return;
     (void)hipSetDevice(s->device);
     (void)hipDeviceSynchronize();
-    for (auto *bf : {&s->W, &s->WT, &s->Wf, &s->x16, &s->h, &s->delta}) bf->release();
+    for (auto *bf : {&s->WT, &s->Wf, &s->x16, &s->h, &s->delta}) bf->release();
     for (auto *bf : {&s->b, &s->wout, &s->bout, &s->master, &s->grad, &s->adam_m, &s->adam_v, &s->xb, &s->yb, &s->ds,
                      &s->out, &s->g, &s->loss, &s->data_x, &s->data_y})
         bf->release();

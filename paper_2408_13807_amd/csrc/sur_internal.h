@@ -18,11 +18,11 @@ constexpr int kIn = 32;        // inputs padded to the MFMA k granularity
 //   off_b:    depth*kWidth          hidden biases
 //   off_wout: kWidth                output weights
 //   off_bout: 1                     output bias
-// The BF16 weights W share the weight part of that layout; WT holds each block transposed,
-// and Wf each block in the order in which inference reads its MFMA fragments (frag_index).
+// The BF16 weights share the weight part of that layout: Wf holds each block in the order
+// in which the forward passes read their MFMA fragments (frag_index), WT each block transposed.
 struct NetView {
     int members, depth;
-    __bf16 *W, *WT, *Wf;
+    __bf16 *WT, *Wf;
     float *b, *wout, *bout;
     size_t w_stride, b_stride, p_stride;
     size_t off_b, off_wout, off_bout;
@@ -67,7 +67,6 @@ __host__ __device__ inline size_t frag_index(size_t o, size_t i, size_t K) {
 // Write one master parameter (member m, flat index q) into the BF16/FP32 copies the kernels read.
 __device__ __forceinline__ void scatter_param(const NetView &v, int m, size_t q, float p) {
     if (q < v.off_b) {
-        v.W[(size_t)m * v.w_stride + q] = (__bf16)p;
         size_t blk, K;
         if (q < (size_t)kWidth * kIn) {
             blk = 0;

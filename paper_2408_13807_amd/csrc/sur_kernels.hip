@@ -72,13 +72,13 @@ __device__ __forceinline__ void layer_fwd(const __bf16 *W, const float *bias, in
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = f32x16{};
+    // W is the layer's block of the fragment-ordered weights (frag_index)
+    const int nst = K >> 4;
+    const __bf16 *wf = W + ((size_t)(wave * 2) * nst * 64 + lane) * 8;
     for (int kk = 0; kk < K; kk += 16) {
         bf16x8 wa[2], hb[4];
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-            const int o = wave * 64 + a * 32 + l32;
-            wa[a] = *reinterpret_cast<const bf16x8 *>(W + (size_t)o * K + kk + 8 * half);
-        }
+        for (int a = 0; a < 2; ++a) wa[a] = *reinterpret_cast<const bf16x8 *>(wf + ((size_t)a * nst + (kk >> 4)) * 512);
 #pragma unroll
         for (int b = 0; b < 4; ++b) hb[b] = *reinterpret_cast<const bf16x8 *>(hin + (b * 32 + l32) * ldin + kk + 8 * half);
 #pragma unroll
@@ -440,7 +440,7 @@ __global__ __launch_bounds__(kThreads) void sur_train_fwd(NetView v, TrainView t
     const int m = blockIdx.y;
     const int64_t n = t.batch;
     const int64_t row0 = (int64_t)blockIdx.x * kR;
-    const __bf16 *W = v.W + (size_t)m * v.w_stride;
+    const __bf16 *W = v.Wf + (size_t)m * v.w_stride;
     const float *b = v.b + (size_t)m * v.b_stride;
     const float *X = t.xb + (size_t)m * n * kFeatures;
     const int64_t ld = t.ld;
