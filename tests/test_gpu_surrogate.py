@@ -127,6 +127,34 @@ def test_predict_models_matches_row_prediction(sur):
     net.close()
 
 
+def test_predict_models_tiles_over_many_models(sur):
+    # models of 0-3 rows (a quarter empty), with a stretch of 0/1-row models so
+    # that a 128-row tile spans more than the 64 model boundaries the kernel
+    # stages: the 64-way search for a tile's first model, the bisection over the
+    # staged boundaries and the walk beyond them, against the row path
+    rng = np.random.default_rng(21)
+    n_models = 3000
+    rows = rng.integers(0, 4, n_models)
+    rows[:400] = rng.integers(0, 2, 400)
+    row_off = np.concatenate([[0], np.cumsum(rows)]).astype(np.int64)
+    model_x = np.column_stack([rng.uniform(-1, 3, n_models), rng.uniform(0, 2, n_models), rng.uniform(-1, 2, n_models),
+                               rng.uniform(-1, 2, n_models), rng.integers(0, 2, n_models)]).astype(np.float32)
+    radius = rng.uniform(1e-3, 1.0, int(row_off[-1])).astype(np.float32)
+    X = np.column_stack([np.repeat(model_x, rows, axis=0), radius]).astype(np.float32)
+    net = sur.SurNet(members=3, depth=4, seed=4)
+    net.set_normalization(X.mean(axis=0), X.std(axis=0), 1.3, 0.4)
+    mean_r, spread_r = net.predict(X)
+    mean_m, spread_m, ms = net.predict_models(model_x, row_off, row_off[:-1], radius)
+    np.testing.assert_array_equal(mean_m, mean_r)
+    np.testing.assert_array_equal(spread_m, spread_r)
+    expect = np.zeros(n_models, np.float32)
+    full = rows > 0
+    expect[full] = np.maximum.reduceat(spread_r, row_off[:-1][full])
+    np.testing.assert_array_equal(ms, expect)
+    assert rows[:400].sum() < 256      # the first tiles hold more than 64 models each
+    net.close()
+
+
 def test_predict_models_rejects_bad_offsets(sur):
     from paper_2408_13807_amd import ire
     net = sur.SurNet(members=2, depth=2, seed=1)
