@@ -168,28 +168,41 @@ def ire_profiles(params: dict, models, package_scale: float = 1.0, chunk: int = 
                  options: dict | None = None, progress=None) -> dict:
     """Per-shell temperatures of study models from batched IRE launches of at
     most `chunk` models each; T of all models end to end with row offsets.
-    `progress(done, total, seconds)` is called after every launch."""
+    `progress(done, total, seconds)` is called after every launch; `seconds`
+    is the wall time of all launches, host preparation included."""
     models = np.asarray(models, np.int64)
-    T, A, secs, pk = [], [], 0.0, 0
+    T, A, pk = [], [], 0
     events = dict.fromkeys(("n_cross", "n_launch", "n_scat", "n_abs"), 0)
     device_ms = 0.0
-    for c0 in range(0, len(models), chunk):
+    t_start = time.perf_counter()
+
+    def make(c0):
         b = _ire.batch_from_workloads(params, models[c0:c0 + chunk], device=device, package_scale=package_scale)
         if options:
             b.set_options(**options)
-        t0 = time.perf_counter()
-        b.run()
-        r = b.results(allow_limit=True)
-        secs += time.perf_counter() - t0
+        return b
+
+    starts = list(range(0, len(models), chunk))
+    cur = make(starts[0]) if starts else None
+    if cur is not None:
+        cur.run()
+    for j, c0 in enumerate(starts):
+        # the next launch's host-side inputs are built while this one runs on the device
+        nxt = make(starts[j + 1]) if j + 1 < len(starts) else None
+        r = cur.results(allow_limit=True)
         pk += int(r["stats"]["n_launch"])
         for k in events:
             events[k] += int(r["stats"][k])
         device_ms += float(r["stats"]["ms_run"])
         T.append(r["T"])
         A.append(r["A"])
-        b.close()
+        cur.close()
         if progress:
-            progress(min(c0 + chunk, len(models)), len(models), secs)
+            progress(min(c0 + chunk, len(models)), len(models), time.perf_counter() - t_start)
+        cur = nxt
+        if cur is not None:
+            cur.run()
+    secs = time.perf_counter() - t_start
     n = params["n"][models].astype(np.int64)
     row_off = np.zeros(len(models) + 1, np.int64)
     np.cumsum(n, out=row_off[1:])

@@ -244,14 +244,29 @@ def study_shells(params: dict, models=None) -> tuple[np.ndarray, np.ndarray]:
     idx = np.arange(len(params["n"])) if models is None else np.asarray(models, np.int64)
     n = params["n"][idx].astype(np.int64)
     central = params["central"][idx].astype(np.int64)
-    grids = {}
-    for k in np.unique(n):
-        grids[(0, int(k))] = np.linspace(0.0, R_OUT, k + 1)
-        grids[(1, int(k))] = np.geomspace(10 * AU, R_OUT, k + 1)
-    edges = [grids[(int(c), int(k))] for c, k in zip(central, n)]
-    r_flat = np.concatenate(edges) if edges else np.zeros(0)
-    lo = np.concatenate([e[:-1] for e in edges]) if edges else np.zeros(0)
-    hi = np.concatenate([e[1:] for e in edges]) if edges else np.zeros(0)
+    if len(idx) == 0:
+        return np.zeros(0), np.zeros(0)
+    # the distinct grids once (linear for external, logarithmic for central
+    # sources), then every model's edges gathered from them
+    uk, inv = np.unique(n, return_inverse=True)
+    tables, g_off, o = [], np.zeros((2, len(uk)), np.int64), 0
+    for c in (0, 1):
+        for u, k in enumerate(uk):
+            g = np.linspace(0.0, R_OUT, k + 1) if c == 0 else np.geomspace(10 * AU, R_OUT, k + 1)
+            tables.append(g)
+            g_off[c, u] = o
+            o += k + 1
+    table = np.concatenate(tables)
+    cnt = n + 1
+    e_off = np.zeros(len(idx), np.int64)
+    np.cumsum(cnt[:-1], out=e_off[1:])
+    src = np.repeat(g_off[central, inv] - e_off, cnt) + np.arange(int(cnt.sum()))
+    r_flat = table[src]
+    first = np.zeros(len(r_flat), bool)
+    first[e_off] = True
+    last = np.zeros(len(r_flat), bool)
+    last[e_off + n] = True
+    lo, hi = r_flat[~last], r_flat[~first]
     rm = 0.5 * (lo + hi)
     p = np.repeat(params["p"][idx], n)
     cen = np.repeat(central, n) == 1

@@ -155,6 +155,22 @@ def test_predict_models_tiles_over_many_models(sur):
     net.close()
 
 
+def test_ire_profiles_in_several_launches(sur):
+    # a long model list runs as several batched launches, each prepared on the
+    # host while the previous one runs: every model gets its own temperatures, in
+    # order (against one launch of all; independent realisations, but the models'
+    # profiles differ by far more than their noise)
+    from paper_2408_13807_amd import workloads as wl
+    params = wl.batch_parameters(23, seed=17)
+    one = sur.ire_profiles(params, range(23), package_scale=0.2)
+    many = sur.ire_profiles(params, range(23), package_scale=0.2, chunk=5)
+    np.testing.assert_array_equal(many["row_off"], one["row_off"])
+    assert many["packages"] == one["packages"]
+    for m in range(23):
+        s = slice(one["row_off"][m], one["row_off"][m + 1])
+        assert np.median(np.abs(many["T"][s] - one["T"][s]) / one["T"][s]) < 0.05, m
+
+
 def test_predict_models_rejects_bad_offsets(sur):
     from paper_2408_13807_amd import ire
     net = sur.SurNet(members=2, depth=2, seed=1)
