@@ -50,18 +50,25 @@ def test_gradients_match_fp64_reference(sur, depth):
     net.close()
 
 
-def test_prediction_matches_reference_forward(sur):
-    net = sur.SurNet(members=3, depth=4, seed=5)
+@pytest.mark.parametrize("members,depth", [(3, 4), (3, 1), (2, 2), (1, 3)])
+def test_prediction_matches_reference_forward(sur, members, depth):
+    # depth 1: the first layer is also the last (its epilogue folds the output
+    # layer); one member: zero spread; 3000 rows: 24 tiles, the last one ragged
+    net = sur.SurNet(members=members, depth=depth, seed=5)
     X, y = _data(3000, seed=2)
     xm, xs = X.mean(axis=0), X.std(axis=0)
     net.set_normalization(xm, xs, 1.2, 0.25)
     P = net.get_params()
     mean, spread = net.predict(X)
-    ref = np.stack([mlp_ref.predict_logT(P[m].astype(np.float64), 4, X, xm, xs, 1.2, 0.25) for m in range(3)])
+    ref = np.stack([mlp_ref.predict_logT(P[m].astype(np.float64), depth, X, xm, xs, 1.2, 0.25)
+                    for m in range(members)])
     assert np.max(np.abs(mean - ref.mean(axis=0))) < 2e-2
-    T = 10.0 ** ref
-    sp = T.std(axis=0, ddof=1) / T.mean(axis=0)
-    assert np.max(np.abs(spread - sp)) < 5e-3 + 0.05 * sp.max()
+    if members > 1:
+        T = 10.0 ** ref
+        sp = T.std(axis=0, ddof=1) / T.mean(axis=0)
+        assert np.max(np.abs(spread - sp)) < 5e-3 + 0.05 * sp.max()
+    else:
+        assert np.all(spread == 0.0)
     net.close()
 
 
