@@ -178,6 +178,33 @@ def test_ire_profiles_in_several_launches(sur):
         assert np.median(np.abs(many["T"][s] - one["T"][s]) / one["T"][s]) < 0.05, m
 
 
+def test_full_size_whole_model_prediction_on_samples(sur):
+    # the benchmark's inference: 10^6 study models (2.1e8 rows, 5 members) in one
+    # launch, sampled models against the FP64 forward, and every model's largest
+    # spread against its rows'
+    from paper_2408_13807_amd import workloads as wl
+    params = wl.batch_parameters(1_000_000, seed=303)
+    q = wl.study_model_inputs(params)
+    net = sur.SurNet(members=5, depth=4, seed=7)
+    Xs, _ = wl.study_features(params, np.arange(0, 1_000_000, 997))
+    xm, xs = Xs.mean(axis=0), Xs.std(axis=0)
+    net.set_normalization(xm, xs, 1.3, 0.4)
+    mean, spread, ms = net.predict_models(q["model_x"], q["row_off"], q["radius_off"], q["radius"])
+    ro = q["row_off"]
+    assert len(mean) == ro[-1] > 2e8
+    assert np.isfinite(mean).all() and np.isfinite(spread).all()
+    P = net.get_params()
+    rng = np.random.default_rng(4)
+    sample = np.concatenate([[0, 999_999], rng.choice(1_000_000, 30, replace=False)])
+    for m in sample:
+        X, _ = wl.study_features(params, [m])
+        ref = np.stack([mlp_ref.predict_logT(P[k].astype(np.float64), 4, X, xm, xs, 1.3, 0.4) for k in range(5)])
+        rows = slice(ro[m], ro[m + 1])
+        assert np.max(np.abs(mean[rows] - ref.mean(axis=0))) < 2e-2, m
+        assert ms[m] == spread[rows].max(), m
+    net.close()
+
+
 def test_predict_models_rejects_bad_offsets(sur):
     from paper_2408_13807_amd import ire
     net = sur.SurNet(members=2, depth=2, seed=1)
