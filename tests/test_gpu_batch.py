@@ -117,6 +117,38 @@ def test_batch_split_models_over_the_study_range(ire, params):
     b.close()
 
 
+def test_full_size_study_launch(ire, params):
+    # the benchmark's launch: all 4096 study models at their full budgets (9.1e9
+    # packages) in one persistent launch with the default schedule; energy
+    # bookkeeping over the whole launch, and sampled models of every kind against
+    # 16 single-model runs of the same budget
+    b = ire.batch_from_workloads(params)
+    b.run()
+    r = b.results()
+    s = r["stats"]
+    assert s["n_models"] == 4096 and s["n_launch"] == int(params["n_pkg"].sum()) > 9e9
+    assert abs((s["escaped"] + s["ffi_escaped"] + s["terminated"]) / s["L_total"] - 1) < 1e-9
+    assert np.isfinite(r["T"]).all() and np.all(r["T"] > 0)
+    Ts, As = split(b, r["T"]), split(b, r["A"])
+    n, tau, cen, npk = params["n"], params["tau_V"], params["central"], params["n_pkg"]
+    cheap = npk < 1_000_000
+    sample = []
+    for mask in ((tau > 100) & (cen == 1), (tau > 100) & (cen == 0), (tau < 1) & (cen == 1), (tau < 1) & (cen == 0),
+                 (n >= 350) & (cen == 1), (n >= 350) & (cen == 0)):
+        sample.append(int(np.nonzero(mask & cheap)[0][0]))
+    for m in sample:
+        mm = wl.batch_model(params, m)
+        key = "n_ps" if cen[m] else "n_ext"
+        runs = [ire.run_model(mm, seed=300 + k, **{key: int(npk[m])}) for k in range(16)]
+        eps = (runs[0]["stats"]["L_ext"] + runs[0]["stats"]["L_ps"]) / int(npk[m])
+        ok, f = mc_stats.compare_runs(Ts[m], [x["T"] for x in runs], [x["A"] for x in runs], name=f"full-size model {m}")
+        print(f"model {m}: {n[m]} shells, tau_V {tau[m]:.2f}, {key} {npk[m]}: {f * 100:.1f}% of shells within "
+              f"max(1%, 3 sigma)", flush=True)
+        assert ok, (m, f)
+        assert mc_stats.zero_deposit_failures(As[m], np.mean([x["A"] for x in runs], axis=0), eps) == [], m
+    b.close()
+
+
 def test_batch_density_dependent_kA(ire, params):
     # Sect. 3.2: absorption scaling by density (k from 3 at each model's lowest
     # density to 1 at its highest) in the batched launch, against single-model
