@@ -197,6 +197,11 @@ def test_parallel_fp32_odd_table_sizes(ire, n_t, K):
     ("ext101_1e8_workgroup", wl.cfg_external_large, dict(n_ext=100_000_000), "ext101_tau10_1e7", dict(aggregate=2)),
     ("central200_1e8_workgroup", wl.cfg_central, dict(n_ps=100_000_000), "central200_tau100_1e7",
      dict(aggregate=2)),
+    # the benchmark's weighted variants: unbiased for the same temperatures
+    ("ext101_1e8_kbg0.2", wl.cfg_external_large, dict(n_ext=100_000_000), "ext101_tau10_1e7", dict(k_bg=0.2)),
+    ("ext101_1e8_ffi", wl.cfg_external_large, dict(n_ext=100_000_000), "ext101_tau10_1e7", dict(ffi=1)),
+    ("ext101_1e8_kbg0.2_ffi", wl.cfg_external_large, dict(n_ext=100_000_000), "ext101_tau10_1e7",
+     dict(k_bg=0.2, ffi=1)),
 ])
 def test_full_size_against_1e7_ensemble(ire, name, factory, npk, gold, opts):
     # full-size runs (as benchmarked) against the oracle's 16-seed ensemble at
@@ -206,7 +211,8 @@ def test_full_size_against_1e7_ensemble(ire, name, factory, npk, gold, opts):
     assert_ensemble_parity(r["T"], g, name=name)
     s = r["stats"]
     out = sum(s["escaped"]) + s["ffi_escaped"] + s["terminated"]
-    assert abs(out / (s["L_ext"] + s["L_ps"]) - 1) < 1e-9
+    # exact bookkeeping unless the background directions are weighted (then in expectation)
+    assert abs(out / (s["L_ext"] + s["L_ps"]) - 1) < (2e-3 if "k_bg" in opts else 1e-9)
     assert s["n_launch"] == sum(npk.values()) and s["n_escape"] == sum(npk.values())
 
 
